@@ -19,7 +19,8 @@
  * A term is included when its Mahalanobis distance q satisfies q <= kappa^2
  * (inclusive); kappa = +inf includes every term.  Side outputs per element:
  *   S     = sum of |terms|
- *   amb   = sum of |terms| whose q lies within 1e-3 kappa^2 of the cutoff
+ *   amb   = sum of |terms| whose q lies within 1e-3 kappa^2 of the cutoff, on
+ *           either side of it (FP32 and FP64 may decide those differently)
  *   npair = number of included terms (summed over the whole call)
  */
 #include <math.h>
@@ -76,12 +77,14 @@ void orc_splat2d(int64_t n_views, int64_t n, const double *rec, /* [V][n][9] */
         for (int a = a0; a <= a1; ++a) {
           double dx = (a + 0.5 - 0.5 * width) * hu + ou - r[0];
           double q = r[2] * dx * dx + 2.0 * r[3] * dx * dy + r[4] * dy * dy;
-          if (!inf && !(q <= k2)) continue;
+          int band = !inf && fabs(q - k2) <= AMB_REL * k2;
+          if (!inf && !(q <= k2) && !band) continue;
           double t = r[5] * exp(-0.5 * q);
           int64_t o = (int64_t)b * width + a;
+          if (Av && band) Av[o] += fabs(t);   /* either side of the cutoff */
+          if (!inf && !(q <= k2)) continue;
           I[o] += t;
           if (Sv) Sv[o] += fabs(t);
-          if (Av && !inf && fabs(q - k2) <= AMB_REL * k2) Av[o] += fabs(t);
           ++np;
         }
       }
@@ -121,7 +124,9 @@ void orc_splat2d_bwd(int64_t n_views, int64_t n, const double *rec, int32_t widt
         for (int a = a0; a <= a1; ++a) {
           double dx = (a + 0.5 - 0.5 * width) * hu + ou - r[0];
           double q = r[2] * dx * dx + 2.0 * r[3] * dx * dy + r[4] * dy * dy;
-          if (!inf && !(q <= k2)) continue;
+          int band = !inf && fabs(q - k2) <= AMB_REL * k2;
+          int in = inf || q <= k2;
+          if (!in && !band) continue;
           double e = exp(-0.5 * q);
           double g = Gv[(int64_t)b * width + a];
           double w = g * r[5] * e;
@@ -132,11 +137,11 @@ void orc_splat2d_bwd(int64_t n_views, int64_t n, const double *rec, int32_t widt
           c[3] = -w * dx * dy;                  /* d/dA01 (enters twice) */
           c[4] = -0.5 * w * dy * dy;            /* d/dA11 */
           c[5] = g * e;                         /* d/drho_hat */
-          int band = !inf && fabs(q - k2) <= AMB_REL * k2;
           for (int k = 0; k < 6; ++k) {
+            if (band) macc[k] += fabs(c[k]);   /* either side of the cutoff */
+            if (!in) continue;
             acc[k] += c[k];
             aacc[k] += fabs(c[k]);
-            if (band) macc[k] += fabs(c[k]);
           }
         }
       }
@@ -190,12 +195,14 @@ void orc_splat3d(int64_t n, const double *rec, int32_t nx, int32_t ny, int32_t n
         for (int i = i0; i <= i1; ++i) {
           double dx = geo[0] + (i + 0.5) * geo[3] - r[0];
           double q = quad3(r + 3, dx, dy, dz);
-          if (!inf && !(q <= k2)) continue;
+          int band = !inf && fabs(q - k2) <= AMB_REL * k2;
+          if (!inf && !(q <= k2) && !band) continue;
           double t = r[9] * exp(-0.5 * q);
           int64_t o = ((int64_t)k * ny + j) * nx + i;
+          if (amb && band) amb[o] += fabs(t);   /* either side of the cutoff */
+          if (!inf && !(q <= k2)) continue;
           vol[o] += t;
           if (S) S[o] += fabs(t);
-          if (amb && !inf && fabs(q - k2) <= AMB_REL * k2) amb[o] += fabs(t);
           ++total;
         }
       }
@@ -233,7 +240,9 @@ void orc_splat3d_bwd(int64_t n, const double *rec, int32_t nx, int32_t ny, int32
         for (int i = i0; i <= i1; ++i) {
           double dx = geo[0] + (i + 0.5) * geo[3] - r[0];
           double q = quad3(P, dx, dy, dz);
-          if (!inf && !(q <= k2)) continue;
+          int band = !inf && fabs(q - k2) <= AMB_REL * k2;
+          int in = inf || q <= k2;
+          if (!in && !band) continue;
           double e = exp(-0.5 * q);
           double h = H[((int64_t)k * ny + j) * nx + i];
           double w = h * r[9] * e;
@@ -248,11 +257,11 @@ void orc_splat3d_bwd(int64_t n, const double *rec, int32_t nx, int32_t ny, int32
           c[7] = -w * dy * dz;
           c[8] = -0.5 * w * dz * dz;
           c[9] = h * e;
-          int band = !inf && fabs(q - k2) <= AMB_REL * k2;
           for (int c2 = 0; c2 < 10; ++c2) {
+            if (band) macc[c2] += fabs(c[c2]);   /* either side of the cutoff */
+            if (!in) continue;
             acc[c2] += c[c2];
             aacc[c2] += fabs(c[c2]);
-            if (band) macc[c2] += fabs(c[c2]);
           }
         }
       }
