@@ -1,0 +1,157 @@
+#!/usr/bin/env python3
+"""Training-iteration throughput of the R^2-Gaussian hot path on one MI355X.
+
+Workload (synthetic, seeded): 200,000 Gaussians on a 12-ellipsoid phantom,
+75 cone-beam views of 512x512 rendered in one launch, loss L1 + 0.25 D-SSIM
+against measured projections (exact line integrals of the phantom), plus
+0.05 TV on a random 64^3 block of a 256^3 voxelization; forward and backward of
+both operators and of the losses.  A step is one such iteration; all of it runs
+in libgs.so.
+
+Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# VALU lane-slots per in-cutoff (view, pixel, Gaussian) term, from the terms'
+# definitions; exp2 is a quarter-rate transcendental and counts 4 slots.
+SLOTS_PER_PAIR = {"render_fwd": 10 + 4, "render_bwd": 18 + 4}
+PEAK_SLOTS_PER_S = 256 * 128 * 2.4e9       # CUs x FP32 lanes per clock x clock (157.3 TFLOP/s / 2)
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, measured, target_s=15.0):
+    """The FP64 oracle on a bounded sample of the same iteration (a subset of
+    the views, all Gaussians, the full TV block), extrapolated to one
+    iteration."""
+    import numpy as np
+    import oracle
+    import workloads
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = max(1, min(threads, os.cpu_count() or 1))
+    nv = len(wl.scan.thetas)
+    k = max(1, min(nv, threads))
+    views = oracle.views_from_scan(wl.scan)[:k]
+    t0 = time.perf_counter()
+    img = oracle.project(wl.gaussians, views, wl.cutoff)["image"]
+    _, _, _, G = oracle.image_loss(img.astype(np.float32), measured[:k], 0.25)
+    oracle.project_grad(wl.gaussians, views, G, wl.cutoff)
+    t_views = time.perf_counter() - t0
+    grid = workloads.tv_block_grid(wl, 0)
+    t1 = time.perf_counter()
+    vol = oracle.voxelize(wl.gaussians, grid, wl.cutoff)["volume"]
+    _, H = oracle.tv_loss(vol.astype(np.float32), 0.05)
+    oracle.voxelize_grad(wl.gaussians, grid, H, wl.cutoff)
+    t_vox = time.perf_counter() - t1
+    t_iter = t_views * nv / k + t_vox
+    return {"value": 1.0 / t_iter, "unit": "iters/s", "cores": threads, "kind": "oracle",
+            "sample": f"{k} of {nv} views (projection fwd, L1+D-SSIM, projection bwd) scaled x{nv / k:.2f}"
+                      f" + the full 64^3 TV block (voxelize fwd, TV, voxelize bwd); measured "
+                      f"{t_views + t_vox:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see the sharding notes in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2405_20693_amd import ops
+    from paper_2405_20693_amd._native import lib
+    from paper_2405_20693_amd.iteration import TrainingIteration
+
+    lib()  # fails loudly if the HIP library is not built
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log("generating workload ...")
+    wl = workloads.c3_iteration()
+    measured = workloads.measured_projections(wl)
+    g = wl.gaussians
+    params = [torch.from_numpy(a).to(dev) for a in (g.mean, g.scale, g.quat, g.density)]
+    views = ops.Views.from_scan(wl.scan)
+    meas_d = torch.from_numpy(measured).to(dev)
+    block = wl.extra["block"]
+    it = TrainingIteration(*params, views, meas_d, (block, block, block), cutoff=wl.cutoff)
+    grids = [ops.grid_from(workloads.tv_block_grid(wl, i)) for i in range(args.warmup + args.steps)]
+    log("warmup ...")
+    for i in range(args.warmup):
+        it.step(grids[i])
+    torch.cuda.synchronize()
+    for p in (it.plan_proj, it.plan_vox, it.plan_loss):
+        p.stage_times()
+        p.set_timing(True)
+    log("timed region ...")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        it.step(grids[args.warmup + i])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = {}
+    for p in (it.plan_proj, it.plan_vox, it.plan_loss):
+        for k, (ms, n) in p.stage_times().items():
+            stages[k] = (stages.get(k, (0.0, 0))[0] + ms, stages.get(k, (0.0, 0))[1] + n)
+    for p in (it.plan_proj, it.plan_vox, it.plan_loss):
+        p.set_timing(False)
+    elapsed = t1 - t0
+    ms_per_step = 1000.0 * elapsed / args.steps
+    loss = float(it.total_loss().cpu())
+    avg = {k: ms / n for k, (ms, n) in stages.items()}
+    log("stage ms/launch: " + ", ".join(f"{k}={v:.3f}" for k, v in sorted(avg.items(), key=lambda x: -x[1])))
+
+    # roofline of the dominant kernel
+    roofline = None
+    gold = os.path.join(ROOT, "tests", "golden", "c3_pairs.json")
+    dom = max(("render_fwd", "render_bwd"), key=lambda k: avg.get(k, 0.0))
+    if os.path.exists(gold):
+        with open(gold) as f:
+            gd = json.load(f)
+        if gd.get("workload") == wl.name:
+            pairs = gd["proj_pairs"]
+            ops_per_launch = pairs * SLOTS_PER_PAIR[dom]
+            achieved = ops_per_launch / (avg[dom] * 1e-3) / 1e12
+            peak = PEAK_SLOTS_PER_S / 1e12
+            roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
+                        "peak": round(peak, 2), "unit": "TOP/s", "frac": round(achieved / peak, 4),
+                        "traffic": None, "pairs_per_launch": pairs,
+                        "ops_per_pair": SLOTS_PER_PAIR[dom], "avg_launch_ms": round(avg[dom], 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(wl, measured)
+
+    out = {"metric": "training iters/sec (fwd+bwd proj+voxelize) at 200k Gaussians",
+           "value": round(args.steps / elapsed, 3), "unit": "iters/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": wl.name, "gaussians": g.n, "views": views.n,
+                      "detector": [views.height, views.width], "tv_block": block,
+                      "tv_grid": wl.extra["full"], "cutoff": wl.cutoff, "loss": "L1+0.25 D-SSIM+0.05 TV"},
+           "roofline": roofline, "cpu_baseline": cpu,
+           "stage_ms": {k: round(v, 4) for k, v in avg.items()}, "final_loss": loss}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,717 @@
+// C ABI of the HIP path: argument validation, plan workspace and the launch
+// sequences of the projection, voxelization and loss entry points.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gs.h"
+#include "internal.h"
+
+using namespace gsk;
+
+namespace {
+
+thread_local std::string g_err;
+
+gs_status fail(gs_status st, const std::string &msg) {
+  g_err = msg;
+  return st;
+}
+
+struct Buf {
+  void *p = nullptr;
+  size_t cap = 0;
+};
+
+struct ProjKey {
+  const float *mean = nullptr, *scale = nullptr, *quat = nullptr, *dens = nullptr;
+  int64_t n = -1;
+  float cutoff = 0.f;
+  std::vector<gs_view> views;
+};
+
+struct VoxKey {
+  const float *mean = nullptr, *scale = nullptr, *quat = nullptr, *dens = nullptr;
+  int64_t n = -1;
+  float cutoff = 0.f;
+  gs_grid grid{};
+};
+
+}  // namespace
+
+struct gs_plan {
+  gs_alloc_fn alloc = nullptr;
+  gs_free_fn free_fn = nullptr;
+  void *ctx = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool used = false;
+  // projection
+  Buf p_views, p_rec, p_hist, p_tile_total, p_tile_start, p_chunk_cnt, p_chunk_start, p_offsets,
+      p_list, p_slots, p_totals;
+  // voxelization
+  Buf v_rec, v_count, v_offsets, v_scan_tmp, v_hist, v_tile_total, v_tile_start, v_list, v_slots,
+      v_totals;
+  // losses
+  Buf l_coef, l_part;
+  Buf skipped;  // unsigned long long [2]: projection, voxelization
+  // host side
+  gs_view *stage = nullptr;          // pinned staging of per-view constants
+  size_t stage_cap = 0;
+  unsigned long long *readback = nullptr;  // pinned, 4 entries
+  hipEvent_t stage_done = nullptr;
+  bool stage_pending = false;
+  // saved forward state
+  bool p_valid = false, v_valid = false;
+  ProjKey pkey;
+  VoxKey vkey;
+  ProjArgs pargs{};
+  VoxArgs vargs{};
+  uint64_t p_entries = 0, v_entries = 0;
+  // per-stage timing
+  bool timing = false;
+  struct Timed {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Timed> timed;
+  std::vector<hipEvent_t> event_pool;
+};
+
+namespace {
+
+hipEvent_t pooled_event(gs_plan *pl) {
+  if (!pl->event_pool.empty()) {
+    hipEvent_t e = pl->event_pool.back();
+    pl->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one stage with two events when the plan times its launches.
+struct StageTimer {
+  gs_plan *pl;
+  hipStream_t s;
+  int stage;
+  hipEvent_t a = nullptr;
+  StageTimer(gs_plan *p, int st, hipStream_t str) : pl(p), s(str), stage(st) {
+    if (pl->timing) {
+      a = pooled_event(pl);
+      if (a) (void)hipEventRecord(a, s);
+    }
+  }
+  void stop() {
+    if (!a) return;
+    hipEvent_t b = pooled_event(pl);
+    if (b) {
+      (void)hipEventRecord(b, s);
+      pl->timed.push_back({stage, a, b});
+    } else {
+      pl->event_pool.push_back(a);
+    }
+    a = nullptr;
+  }
+  ~StageTimer() { stop(); }
+};
+
+gs_status sync_stream(gs_plan *pl, hipStream_t s) {
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(GS_EHIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+  return GS_OK;
+}
+
+void release(gs_plan *pl, Buf &b) {
+  if (!b.p) return;
+  if (pl->free_fn)
+    pl->free_fn(b.p, pl->ctx);
+  else
+    (void)hipFree(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+}
+
+// Grow-only workspace buffer.  Growing synchronizes `s` first so that no
+// queued kernel still uses the old buffer.
+gs_status ensure(gs_plan *pl, Buf &b, size_t bytes, hipStream_t s) {
+  if (bytes == 0) bytes = 256;
+  if (b.cap >= bytes) return GS_OK;
+  if (b.p) {
+    gs_status st = sync_stream(pl, s);
+    if (st != GS_OK) return st;
+    release(pl, b);
+  }
+  size_t want = bytes + bytes / 4;
+  want = (want + 255) & ~(size_t)255;
+  void *p = nullptr;
+  if (pl->alloc) {
+    p = pl->alloc(want, pl->ctx);
+  } else if (hipMalloc(&p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+  }
+  if (!p) return fail(GS_ENOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed");
+  b.p = p;
+  b.cap = want;
+  return GS_OK;
+}
+
+gs_status check_launch(const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(GS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  return GS_OK;
+}
+
+#define GS_TRY(x)                   \
+  do {                              \
+    gs_status _st = (x);            \
+    if (_st != GS_OK) return _st;   \
+  } while (0)
+
+template <class T> T *P(Buf &b) { return reinterpret_cast<T *>(b.p); }
+
+bool finite_pos(float x) { return std::isfinite(x) && x > 0.f; }
+
+gs_status check_gaussians(const gs_gaussians *g) {
+  if (!g) return fail(GS_EINVAL, "gaussians is NULL");
+  if (g->n < 0) return fail(GS_EINVAL, "gaussians->n < 0");
+  if (g->n > 0x7fffffffLL) return fail(GS_EUNSUPPORTED, "more than 2^31-1 Gaussians");
+  if (g->n > 0 && (!g->mean || !g->scale || !g->quat || !g->density))
+    return fail(GS_EINVAL, "a Gaussian array pointer is NULL");
+  return GS_OK;
+}
+
+gs_status check_cutoff(float cutoff) {
+  if (!(cutoff > 0.f)) return fail(GS_EINVAL, "cutoff must be > 0 (INFINITY for none)");
+  return GS_OK;
+}
+
+gs_status check_views(const gs_view *views, int32_t n_views) {
+  if (!views) return fail(GS_EINVAL, "views is NULL");
+  if (n_views < 1) return fail(GS_EINVAL, "n_views < 1");
+  const int w = views[0].width, h = views[0].height;
+  for (int i = 0; i < n_views; ++i) {
+    const gs_view &v = views[i];
+    const std::string at = " (view " + std::to_string(i) + ")";
+    if (v.beam != GS_PARALLEL && v.beam != GS_CONE) return fail(GS_EINVAL, "unknown beam" + at);
+    if (v.width < 1 || v.height < 1 || v.width > 16384 || v.height > 16384)
+      return fail(GS_EINVAL, "detector size out of 1..16384" + at);
+    if (v.width != w || v.height != h) return fail(GS_EINVAL, "views differ in detector size" + at);
+    if (!finite_pos(v.pitch_u) || !finite_pos(v.pitch_v)) return fail(GS_EINVAL, "pitch must be > 0" + at);
+    if (!std::isfinite(v.off_u) || !std::isfinite(v.off_v)) return fail(GS_EINVAL, "offset not finite" + at);
+    for (int k = 0; k < 9; ++k)
+      if (!std::isfinite(v.rot[k])) return fail(GS_EINVAL, "rotation not finite" + at);
+    if (v.beam == GS_CONE) {
+      if (!finite_pos(v.src_obj) || !std::isfinite(v.src_det) || !(v.src_det > v.src_obj))
+        return fail(GS_EINVAL, "cone beam needs 0 < src_obj < src_det" + at);
+    }
+  }
+  return GS_OK;
+}
+
+gs_status check_grid(const gs_grid *grid) {
+  if (!grid) return fail(GS_EINVAL, "grid is NULL");
+  if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1 || grid->nx > 16384 || grid->ny > 16384 ||
+      grid->nz > 16384)
+    return fail(GS_EINVAL, "grid size out of 1..16384");
+  for (int k = 0; k < 3; ++k) {
+    if (!finite_pos(grid->spacing[k])) return fail(GS_EINVAL, "grid spacing must be > 0");
+    if (!std::isfinite(grid->origin[k])) return fail(GS_EINVAL, "grid origin not finite");
+  }
+  return GS_OK;
+}
+
+DevView make_dev_view(const gs_view &v) {
+  DevView d{};
+  for (int k = 0; k < 9; ++k) d.W[k] = v.rot[k];
+  d.L_SO = v.src_obj;
+  d.L_SD = v.src_det;
+  d.hu = v.pitch_u;
+  d.hv = v.pitch_v;
+  d.inv_hu = (float)(1.0 / (double)v.pitch_u);
+  d.inv_hv = (float)(1.0 / (double)v.pitch_v);
+  d.cu = (float)(0.5 * v.width - 0.5 - (double)v.off_u / (double)v.pitch_u);
+  d.cv = (float)(0.5 * v.height - 0.5 - (double)v.off_v / (double)v.pitch_v);
+  d.beam = v.beam;
+  return d;
+}
+
+void cutoff_consts(float cutoff, float &kappa, float &thr, float &qmax) {
+  kappa = cutoff;
+  if (std::isinf(cutoff)) {
+    thr = -INFINITY;
+    qmax = INFINITY;
+  } else {
+    double q = 0.5 * 1.4426950408889634 * (double)cutoff * (double)cutoff;
+    thr = (float)(-q);
+    qmax = (float)(q * (1.0 + 1e-5));
+  }
+}
+
+// Uploads per-view constants through the pinned staging buffer.
+gs_status upload_views(gs_plan *pl, const gs_view *views, int32_t nv, hipStream_t s) {
+  size_t bytes = sizeof(DevView) * (size_t)nv;
+  GS_TRY(ensure(pl, pl->p_views, bytes, s));
+  if (pl->stage_pending) {
+    if (hipEventSynchronize(pl->stage_done) != hipSuccess) return fail(GS_EHIP, "hipEventSynchronize");
+    pl->stage_pending = false;
+  }
+  if (pl->stage_cap < bytes) {
+    if (pl->stage) (void)hipHostFree(pl->stage);
+    pl->stage = nullptr;
+    pl->stage_cap = 0;
+    if (hipHostMalloc((void **)&pl->stage, bytes, hipHostMallocDefault) != hipSuccess)
+      return fail(GS_ENOMEM, "pinned staging allocation failed");
+    pl->stage_cap = bytes;
+  }
+  DevView *dv = reinterpret_cast<DevView *>(pl->stage);
+  for (int i = 0; i < nv; ++i) dv[i] = make_dev_view(views[i]);
+  if (hipMemcpyAsync(pl->p_views.p, pl->stage, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+    return fail(GS_EHIP, "view upload failed");
+  if (hipEventRecord(pl->stage_done, s) != hipSuccess) return fail(GS_EHIP, "hipEventRecord");
+  pl->stage_pending = true;
+  return GS_OK;
+}
+
+bool same_proj(const gs_plan *pl, const gs_gaussians *g, const gs_view *views, int32_t nv,
+               float cutoff) {
+  const ProjKey &k = pl->pkey;
+  if (!pl->p_valid || k.mean != g->mean || k.scale != g->scale || k.quat != g->quat ||
+      k.dens != g->density || k.n != g->n || k.cutoff != cutoff || (int32_t)k.views.size() != nv)
+    return false;
+  return std::memcmp(k.views.data(), views, sizeof(gs_view) * (size_t)nv) == 0;
+}
+
+bool same_vox(const gs_plan *pl, const gs_gaussians *g, const gs_grid *grid, float cutoff) {
+  const VoxKey &k = pl->vkey;
+  return pl->v_valid && k.mean == g->mean && k.scale == g->scale && k.quat == g->quat &&
+         k.dens == g->density && k.n == g->n && k.cutoff == cutoff &&
+         std::memcmp(&k.grid, grid, sizeof(gs_grid)) == 0;
+}
+
+// Projection + binning: records, tile lists and backward slot offsets.
+gs_status proj_bin(gs_plan *pl, const gs_gaussians *g, const gs_view *views, int32_t nv,
+                   float cutoff, hipStream_t s) {
+  pl->p_valid = false;
+  ProjArgs a{};
+  a.mean = g->mean; a.scale = g->scale; a.quat = g->quat; a.dens = g->density;
+  a.M = g->n;
+  a.V = nv;
+  a.width = views[0].width;
+  a.height = views[0].height;
+  a.TX = (a.width + kTile - 1) / kTile;
+  a.TY = (a.height + kTile - 1) / kTile;
+  a.T = a.TX * a.TY;
+  if (a.T > kMaxTilesPerGroup)
+    return fail(GS_EUNSUPPORTED, "detector has more than 16384 tiles of 16x16 pixels");
+  a.C = (int)((a.M + kChunk - 1) / kChunk);
+  cutoff_consts(cutoff, a.kappa, a.thr, a.qmax);
+  const int64_t VM = (int64_t)nv * a.M, VT = (int64_t)nv * a.T, VC = (int64_t)nv * a.C;
+  if (VT + 1 > 0x7fffffffLL || VC + 1 > 0x7fffffffLL)
+    return fail(GS_EUNSUPPORTED, "too many views in one call");
+  GS_TRY(upload_views(pl, views, nv, s));
+  a.views = P<DevView>(pl->p_views);
+  GS_TRY(ensure(pl, pl->p_rec, sizeof(Rec2) * VM, s));
+  GS_TRY(ensure(pl, pl->p_hist, 4 * VC * a.T, s));
+  GS_TRY(ensure(pl, pl->p_tile_total, 4 * VT, s));
+  GS_TRY(ensure(pl, pl->p_tile_start, 4 * (VT + 1), s));
+  GS_TRY(ensure(pl, pl->p_chunk_cnt, 4 * VC, s));
+  GS_TRY(ensure(pl, pl->p_chunk_start, 4 * (VC + 1), s));
+  GS_TRY(ensure(pl, pl->p_offsets, 4 * VM, s));
+  GS_TRY(ensure(pl, pl->p_totals, 16, s));
+  GS_TRY(ensure(pl, pl->skipped, 16, s));
+  if (hipMemsetAsync(pl->skipped.p, 0, 8, s) != hipSuccess) return fail(GS_EHIP, "hipMemsetAsync");
+  StageTimer t_bin(pl, GS_STAGE_PROJ_BIN, s);
+  launch_proj_hist(a, P<Rec2>(pl->p_rec), P<uint32_t>(pl->p_hist), P<uint32_t>(pl->p_chunk_cnt),
+                   P<unsigned long long>(pl->skipped), s);
+  launch_hist_colscan(nv, a.C, a.T, P<uint32_t>(pl->p_hist), P<uint32_t>(pl->p_tile_total), s);
+  launch_scan2(P<uint32_t>(pl->p_tile_total), P<uint32_t>(pl->p_tile_start), (int)VT,
+               P<uint32_t>(pl->p_chunk_cnt), P<uint32_t>(pl->p_chunk_start), (int)VC,
+               P<unsigned long long>(pl->p_totals), s);
+  t_bin.stop();
+  GS_TRY(check_launch("projection binning"));
+  if (hipMemcpyAsync(pl->readback, pl->p_totals.p, 16, hipMemcpyDeviceToHost, s) != hipSuccess)
+    return fail(GS_EHIP, "entry count readback failed");
+  GS_TRY(sync_stream(pl, s));
+  const unsigned long long entries = pl->readback[0];
+  if (entries != pl->readback[1])
+    return fail(GS_EHIP, "internal error: tile and Gaussian entry totals differ");
+  if (entries >= 0xffffffffull)
+    return fail(GS_EOVERFLOW, "more than 2^32-1 tile entries: split the views over several calls");
+  GS_TRY(ensure(pl, pl->p_list, 4 * (size_t)entries, s));
+  StageTimer t_sc(pl, GS_STAGE_PROJ_SCATTER, s);
+  launch_proj_scatter(a, P<Rec2>(pl->p_rec), P<uint32_t>(pl->p_hist), P<uint32_t>(pl->p_tile_start),
+                      P<uint32_t>(pl->p_chunk_start), P<uint32_t>(pl->p_list),
+                      P<uint32_t>(pl->p_offsets), s);
+  t_sc.stop();
+  GS_TRY(check_launch("projection scatter"));
+  pl->pargs = a;
+  pl->p_entries = entries;
+  pl->pkey.mean = g->mean; pl->pkey.scale = g->scale; pl->pkey.quat = g->quat;
+  pl->pkey.dens = g->density; pl->pkey.n = g->n; pl->pkey.cutoff = cutoff;
+  pl->pkey.views.assign(views, views + nv);
+  pl->p_valid = true;
+  return GS_OK;
+}
+
+gs_status vox_bin(gs_plan *pl, const gs_gaussians *g, const gs_grid *grid, float cutoff,
+                  hipStream_t s) {
+  pl->v_valid = false;
+  VoxArgs a{};
+  a.mean = g->mean; a.scale = g->scale; a.quat = g->quat; a.dens = g->density;
+  a.M = g->n;
+  a.nx = grid->nx; a.ny = grid->ny; a.nz = grid->nz;
+  for (int k = 0; k < 3; ++k) {
+    a.origin[k] = grid->origin[k];
+    a.spacing[k] = grid->spacing[k];
+  }
+  a.TX = (a.nx + kVTile - 1) / kVTile;
+  a.TY = (a.ny + kVTile - 1) / kVTile;
+  a.TZ = (a.nz + kVTile - 1) / kVTile;
+  const int plane = a.TX * a.TY;
+  if (plane > kMaxTilesPerGroup) return fail(GS_EUNSUPPORTED, "grid plane has more than 16384 tiles");
+  a.layers = std::max(1, std::min(a.TZ, 4096 / plane));
+  a.G = (a.TZ + a.layers - 1) / a.layers;
+  a.Tg = plane * a.layers;
+  a.C = (int)((a.M + kChunk - 1) / kChunk);
+  cutoff_consts(cutoff, a.kappa, a.thr, a.qmax);
+  const int64_t GT = (int64_t)a.G * a.Tg, GC = (int64_t)a.G * a.C;
+  const int64_t nb = (a.M + 4095) / 4096 + 1;
+  GS_TRY(ensure(pl, pl->v_rec, sizeof(Rec3) * (size_t)a.M, s));
+  GS_TRY(ensure(pl, pl->v_count, 4 * (size_t)a.M, s));
+  GS_TRY(ensure(pl, pl->v_offsets, 4 * (size_t)(a.M + 1), s));
+  GS_TRY(ensure(pl, pl->v_scan_tmp, 4 * (size_t)(2 * nb + 1), s));
+  GS_TRY(ensure(pl, pl->v_hist, 4 * (size_t)(GC * a.Tg), s));
+  GS_TRY(ensure(pl, pl->v_tile_total, 4 * (size_t)GT, s));
+  GS_TRY(ensure(pl, pl->v_tile_start, 4 * (size_t)(GT + 1), s));
+  GS_TRY(ensure(pl, pl->v_totals, 16, s));
+  GS_TRY(ensure(pl, pl->skipped, 16, s));
+  if (hipMemsetAsync(P<unsigned long long>(pl->skipped) + 1, 0, 8, s) != hipSuccess)
+    return fail(GS_EHIP, "hipMemsetAsync");
+  StageTimer t_bin(pl, GS_STAGE_VOX_BIN, s);
+  launch_vox_records(a, P<Rec3>(pl->v_rec), P<uint32_t>(pl->v_count),
+                     P<unsigned long long>(pl->skipped) + 1, s);
+  launch_scan_big(P<uint32_t>(pl->v_count), P<uint32_t>(pl->v_offsets), a.M,
+                  P<uint32_t>(pl->v_scan_tmp), P<unsigned long long>(pl->v_totals) + 1, s);
+  launch_vox_hist(a, P<Rec3>(pl->v_rec), P<uint32_t>(pl->v_hist), s);
+  launch_hist_colscan(a.G, a.C, a.Tg, P<uint32_t>(pl->v_hist), P<uint32_t>(pl->v_tile_total), s);
+  launch_scan2(P<uint32_t>(pl->v_tile_total), P<uint32_t>(pl->v_tile_start), (int)GT, nullptr,
+               nullptr, 0, P<unsigned long long>(pl->v_totals), s);
+  t_bin.stop();
+  GS_TRY(check_launch("voxel binning"));
+  if (hipMemcpyAsync(pl->readback, pl->v_totals.p, 16, hipMemcpyDeviceToHost, s) != hipSuccess)
+    return fail(GS_EHIP, "entry count readback failed");
+  GS_TRY(sync_stream(pl, s));
+  const unsigned long long entries = pl->readback[0];
+  if (entries != pl->readback[1])
+    return fail(GS_EHIP, "internal error: tile and Gaussian entry totals differ");
+  if (entries >= 0xffffffffull) return fail(GS_EOVERFLOW, "more than 2^32-1 voxel tile entries");
+  GS_TRY(ensure(pl, pl->v_list, 4 * (size_t)entries, s));
+  StageTimer t_sc(pl, GS_STAGE_VOX_SCATTER, s);
+  launch_vox_scatter(a, P<Rec3>(pl->v_rec), P<uint32_t>(pl->v_hist), P<uint32_t>(pl->v_tile_start),
+                     P<uint32_t>(pl->v_list), s);
+  t_sc.stop();
+  GS_TRY(check_launch("voxel scatter"));
+  pl->vargs = a;
+  pl->v_entries = entries;
+  pl->vkey.mean = g->mean; pl->vkey.scale = g->scale; pl->vkey.quat = g->quat;
+  pl->vkey.dens = g->density; pl->vkey.n = g->n; pl->vkey.cutoff = cutoff;
+  pl->vkey.grid = *grid;
+  pl->v_valid = true;
+  return GS_OK;
+}
+
+struct TempPlan {
+  gs_plan *p = nullptr;
+  bool owned = false;
+  ~TempPlan() {
+    if (owned && p) gs_plan_destroy(p);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char *gs_last_error(void) { return g_err.c_str(); }
+
+gs_status gs_plan_create(gs_alloc_fn alloc, gs_free_fn free_fn, void *ctx, gs_plan **out) {
+  if (!out) return fail(GS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if ((alloc == nullptr) != (free_fn == nullptr))
+    return fail(GS_EINVAL, "give both alloc and free, or neither");
+  gs_plan *p = new (std::nothrow) gs_plan();
+  if (!p) return fail(GS_ENOMEM, "plan allocation failed");
+  p->alloc = alloc;
+  p->free_fn = free_fn;
+  p->ctx = ctx;
+  if (hipHostMalloc((void **)&p->readback, 4 * sizeof(unsigned long long), hipHostMallocDefault) !=
+      hipSuccess) {
+    delete p;
+    return fail(GS_EHIP, "pinned readback allocation failed");
+  }
+  if (hipEventCreateWithFlags(&p->stage_done, hipEventDisableTiming) != hipSuccess) {
+    (void)hipHostFree(p->readback);
+    delete p;
+    return fail(GS_EHIP, "hipEventCreate failed");
+  }
+  *out = p;
+  return GS_OK;
+}
+
+void gs_plan_destroy(gs_plan *p) {
+  if (!p) return;
+  if (p->used && p->last_stream != nullptr) (void)hipStreamSynchronize(p->last_stream);
+  if (p->used) (void)hipDeviceSynchronize();
+  Buf *bufs[] = {&p->p_views, &p->p_rec, &p->p_hist, &p->p_tile_total, &p->p_tile_start,
+                 &p->p_chunk_cnt, &p->p_chunk_start, &p->p_offsets, &p->p_list, &p->p_slots,
+                 &p->p_totals, &p->v_rec, &p->v_count, &p->v_offsets, &p->v_scan_tmp, &p->v_hist,
+                 &p->v_tile_total, &p->v_tile_start, &p->v_list, &p->v_slots, &p->v_totals,
+                 &p->l_coef, &p->l_part, &p->skipped};
+  for (Buf *b : bufs) release(p, *b);
+  if (p->stage) (void)hipHostFree(p->stage);
+  if (p->readback) (void)hipHostFree(p->readback);
+  if (p->stage_done) (void)hipEventDestroy(p->stage_done);
+  for (auto &t : p->timed) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
+  delete p;
+}
+
+gs_status gs_plan_status(gs_plan *p, int64_t *skipped, int64_t *tile_entries) {
+  if (!p) return fail(GS_EINVAL, "plan is NULL");
+  if (skipped) *skipped = 0;
+  if (tile_entries) *tile_entries = (int64_t)(p->p_valid ? p->p_entries : 0) +
+                                    (int64_t)(p->v_valid ? p->v_entries : 0);
+  if (!p->used || !p->skipped.p) return GS_OK;
+  GS_TRY(sync_stream(p, p->last_stream));
+  unsigned long long h[2] = {0, 0};
+  if (hipMemcpy(h, p->skipped.p, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(GS_EHIP, "status readback failed");
+  if (skipped) *skipped = (int64_t)(h[0] + h[1]);
+  return GS_OK;
+}
+
+gs_status gs_plan_set_timing(gs_plan *p, int32_t enable) {
+  if (!p) return fail(GS_EINVAL, "plan is NULL");
+  p->timing = enable != 0;
+  return GS_OK;
+}
+
+gs_status gs_plan_stage_times(gs_plan *p, double *ms_sum, int64_t *count, int32_t n) {
+  if (!p) return fail(GS_EINVAL, "plan is NULL");
+  if (n < 0 || n > GS_N_STAGES || (n > 0 && (!ms_sum || !count)))
+    return fail(GS_EINVAL, "bad output arrays");
+  for (int i = 0; i < n; ++i) {
+    ms_sum[i] = 0.0;
+    count[i] = 0;
+  }
+  if (p->used && !p->timed.empty()) GS_TRY(sync_stream(p, p->last_stream));
+  gs_status st = GS_OK;
+  for (auto &t : p->timed) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t.a, t.b) != hipSuccess)
+      st = fail(GS_EHIP, "hipEventElapsedTime failed");
+    else if (t.stage < n) {
+      ms_sum[t.stage] += ms;
+      count[t.stage] += 1;
+    }
+    p->event_pool.push_back(t.a);
+    p->event_pool.push_back(t.b);
+  }
+  p->timed.clear();
+  return st;
+}
+
+gs_status gs_view_cone(double theta, float src_obj, float src_det, int32_t width, int32_t height,
+                       float pitch, gs_view *out) {
+  if (!out) return fail(GS_EINVAL, "out is NULL");
+  if (!std::isfinite(theta)) return fail(GS_EINVAL, "theta not finite");
+  if (!finite_pos(src_obj) || !std::isfinite(src_det) || !(src_det > src_obj))
+    return fail(GS_EINVAL, "need 0 < src_obj < src_det");
+  if (width < 1 || height < 1 || width > 16384 || height > 16384)
+    return fail(GS_EINVAL, "detector size out of 1..16384");
+  if (!finite_pos(pitch)) return fail(GS_EINVAL, "pitch must be > 0");
+  const double s = std::sin(theta), c = std::cos(theta);
+  const double W[9] = {-s, c, 0.0, 0.0, 0.0, -1.0, -c, -s, 0.0};
+  std::memset(out, 0, sizeof(*out));
+  out->beam = GS_CONE;
+  out->width = width;
+  out->height = height;
+  out->pitch_u = out->pitch_v = pitch;
+  for (int k = 0; k < 9; ++k) out->rot[k] = (float)W[k];
+  out->src_obj = src_obj;
+  out->src_det = src_det;
+  return GS_OK;
+}
+
+gs_status gs_project_fwd(const gs_gaussians *g, const gs_view *views, int32_t n_views, float cutoff,
+                         float *image, gs_plan *plan, hipStream_t stream) {
+  GS_TRY(check_gaussians(g));
+  GS_TRY(check_views(views, n_views));
+  GS_TRY(check_cutoff(cutoff));
+  if (!image) return fail(GS_EINVAL, "image is NULL");
+  TempPlan tp;
+  if (!plan) {
+    GS_TRY(gs_plan_create(nullptr, nullptr, nullptr, &tp.p));
+    tp.owned = true;
+    plan = tp.p;
+  }
+  plan->used = true;
+  plan->last_stream = stream;
+  const size_t pix = (size_t)n_views * views[0].width * views[0].height;
+  if (g->n == 0) {
+    plan->p_valid = false;
+    if (hipMemsetAsync(image, 0, sizeof(float) * pix, stream) != hipSuccess)
+      return fail(GS_EHIP, "hipMemsetAsync");
+    return tp.owned ? sync_stream(plan, stream) : GS_OK;
+  }
+  GS_TRY(proj_bin(plan, g, views, n_views, cutoff, stream));
+  {
+    StageTimer t(plan, GS_STAGE_RENDER_FWD, stream);
+    launch_render_fwd(plan->pargs, P<Rec2>(plan->p_rec), P<uint32_t>(plan->p_list),
+                      P<uint32_t>(plan->p_tile_start), image, stream);
+  }
+  GS_TRY(check_launch("render forward"));
+  if (tp.owned) GS_TRY(sync_stream(plan, stream));
+  return GS_OK;
+}
+
+gs_status gs_project_bwd(const gs_gaussians *g, const gs_view *views, int32_t n_views, float cutoff,
+                         const float *grad_image, const gs_grads *grads, int32_t accumulate,
+                         gs_plan *plan, hipStream_t stream) {
+  GS_TRY(check_gaussians(g));
+  GS_TRY(check_views(views, n_views));
+  GS_TRY(check_cutoff(cutoff));
+  if (!grad_image) return fail(GS_EINVAL, "grad_image is NULL");
+  if (!grads) return fail(GS_EINVAL, "grads is NULL");
+  if (!plan) return fail(GS_EINVAL, "plan is NULL");
+  plan->used = true;
+  plan->last_stream = stream;
+  if (g->n == 0) return GS_OK;
+  if (!same_proj(plan, g, views, n_views, cutoff))
+    GS_TRY(proj_bin(plan, g, views, n_views, cutoff, stream));
+  const ProjArgs &a = plan->pargs;
+  GS_TRY(ensure(plan, plan->p_slots, 24 * (size_t)plan->p_entries, stream));
+  {
+    StageTimer t(plan, GS_STAGE_RENDER_BWD, stream);
+    launch_render_bwd(a, P<Rec2>(plan->p_rec), P<uint32_t>(plan->p_list),
+                      P<uint32_t>(plan->p_tile_start), P<uint32_t>(plan->p_offsets), grad_image,
+                      P<float>(plan->p_slots), stream);
+  }
+  {
+    StageTimer t(plan, GS_STAGE_PROJ_CHAIN, stream);
+    launch_proj_chain(a, P<Rec2>(plan->p_rec), P<uint32_t>(plan->p_offsets),
+                      P<float>(plan->p_slots), grads->mean, grads->scale, grads->quat,
+                      grads->density, accumulate, stream);
+  }
+  return check_launch("projection backward");
+}
+
+gs_status gs_voxelize_fwd(const gs_gaussians *g, const gs_grid *grid, float cutoff, float *volume,
+                          gs_plan *plan, hipStream_t stream) {
+  GS_TRY(check_gaussians(g));
+  GS_TRY(check_grid(grid));
+  GS_TRY(check_cutoff(cutoff));
+  if (!volume) return fail(GS_EINVAL, "volume is NULL");
+  TempPlan tp;
+  if (!plan) {
+    GS_TRY(gs_plan_create(nullptr, nullptr, nullptr, &tp.p));
+    tp.owned = true;
+    plan = tp.p;
+  }
+  plan->used = true;
+  plan->last_stream = stream;
+  const size_t nvox = (size_t)grid->nx * grid->ny * grid->nz;
+  if (g->n == 0) {
+    plan->v_valid = false;
+    if (hipMemsetAsync(volume, 0, sizeof(float) * nvox, stream) != hipSuccess)
+      return fail(GS_EHIP, "hipMemsetAsync");
+    return tp.owned ? sync_stream(plan, stream) : GS_OK;
+  }
+  GS_TRY(vox_bin(plan, g, grid, cutoff, stream));
+  {
+    StageTimer t(plan, GS_STAGE_VOX_FWD, stream);
+    launch_vox_fwd(plan->vargs, P<Rec3>(plan->v_rec), P<uint32_t>(plan->v_list),
+                   P<uint32_t>(plan->v_tile_start), volume, stream);
+  }
+  GS_TRY(check_launch("voxelize forward"));
+  if (tp.owned) GS_TRY(sync_stream(plan, stream));
+  return GS_OK;
+}
+
+gs_status gs_voxelize_bwd(const gs_gaussians *g, const gs_grid *grid, float cutoff,
+                          const float *grad_volume, const gs_grads *grads, int32_t accumulate,
+                          gs_plan *plan, hipStream_t stream) {
+  GS_TRY(check_gaussians(g));
+  GS_TRY(check_grid(grid));
+  GS_TRY(check_cutoff(cutoff));
+  if (!grad_volume) return fail(GS_EINVAL, "grad_volume is NULL");
+  if (!grads) return fail(GS_EINVAL, "grads is NULL");
+  if (!plan) return fail(GS_EINVAL, "plan is NULL");
+  plan->used = true;
+  plan->last_stream = stream;
+  if (g->n == 0) return GS_OK;
+  if (!same_vox(plan, g, grid, cutoff)) GS_TRY(vox_bin(plan, g, grid, cutoff, stream));
+  const VoxArgs &a = plan->vargs;
+  GS_TRY(ensure(plan, plan->v_slots, 40 * (size_t)plan->v_entries, stream));
+  {
+    StageTimer t(plan, GS_STAGE_VOX_BWD, stream);
+    launch_vox_bwd(a, P<Rec3>(plan->v_rec), P<uint32_t>(plan->v_list),
+                   P<uint32_t>(plan->v_tile_start), P<uint32_t>(plan->v_offsets), grad_volume,
+                   P<float>(plan->v_slots), stream);
+  }
+  {
+    StageTimer t(plan, GS_STAGE_VOX_CHAIN, stream);
+    launch_vox_chain(a, P<Rec3>(plan->v_rec), P<uint32_t>(plan->v_offsets),
+                     P<float>(plan->v_slots), grads->mean, grads->scale, grads->quat,
+                     grads->density, accumulate, stream);
+  }
+  return check_launch("voxelize backward");
+}
+
+gs_status gs_loss_image(const float *render, const float *measured, int32_t n_img, int32_t h,
+                        int32_t w, float lambda_ssim, float *loss_out, float *grad, gs_plan *plan,
+                        hipStream_t stream) {
+  if (!render || !measured || !loss_out) return fail(GS_EINVAL, "NULL array argument");
+  if (n_img < 1 || h < 1 || w < 1) return fail(GS_EINVAL, "sizes must be >= 1");
+  if (!std::isfinite(lambda_ssim)) return fail(GS_EINVAL, "lambda_ssim not finite");
+  if (!plan) return fail(GS_EINVAL, "plan is NULL");
+  plan->used = true;
+  plan->last_stream = stream;
+  const size_t N = (size_t)n_img * h * w;
+  const int nb = ssim_num_blocks(n_img, h, w);
+  GS_TRY(ensure(plan, plan->l_coef, 3 * sizeof(float) * N, stream));
+  GS_TRY(ensure(plan, plan->l_part, 2 * sizeof(float) * (size_t)nb, stream));
+  StageTimer t(plan, GS_STAGE_LOSS_IMAGE, stream);
+  launch_ssim_coeffs(render, measured, n_img, h, w, P<float>(plan->l_coef), P<float>(plan->l_part),
+                     stream);
+  launch_loss_finish(P<float>(plan->l_part), nb, n_img, h, w, lambda_ssim, loss_out, stream);
+  if (grad)
+    launch_ssim_grad(render, measured, P<float>(plan->l_coef), n_img, h, w, lambda_ssim, grad, stream);
+  return check_launch("image loss");
+}
+
+gs_status gs_loss_tv(const float *volume, int32_t nx, int32_t ny, int32_t nz, float weight,
+                     float *loss_out, float *grad, int32_t accumulate, gs_plan *plan,
+                     hipStream_t stream) {
+  if (!volume || !loss_out) return fail(GS_EINVAL, "NULL array argument");
+  if (nx < 1 || ny < 1 || nz < 1) return fail(GS_EINVAL, "sizes must be >= 1");
+  if (!std::isfinite(weight)) return fail(GS_EINVAL, "weight not finite");
+  if (!plan) return fail(GS_EINVAL, "plan is NULL");
+  plan->used = true;
+  plan->last_stream = stream;
+  const int nb = tv_num_blocks(nx, ny, nz);
+  GS_TRY(ensure(plan, plan->l_part, sizeof(float) * (size_t)nb, stream));
+  int n_part = 0;
+  StageTimer t(plan, GS_STAGE_LOSS_TV, stream);
+  launch_tv(volume, nx, ny, nz, weight, grad, accumulate, P<float>(plan->l_part), &n_part, stream);
+  launch_tv_finish(P<float>(plan->l_part), n_part, loss_out, stream);
+  return check_launch("total variation");
+}
+
+}  // extern "C"

@@ -1,0 +1,535 @@
+// X-ray rasterizer kernels: per-(view, Gaussian) projection with tile
+// histograms, tile-list scatter, tile render forward/backward and the
+// per-Gaussian chain rule (paper Sec. 3.2.1, Eq. 5-7, App. A).
+#include "internal.h"
+
+namespace gsk {
+
+// ----------------------------------------------------------- primitives --
+
+__device__ inline uint32_t wave_incl_scan(uint32_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
+// Exclusive scan over a 256-thread workgroup; all threads must call it.
+__device__ inline uint32_t block_excl_scan(uint32_t x, uint32_t *sh4, uint32_t &total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t inc = wave_incl_scan(x);
+  if (lane == 63) sh4[w] = inc;
+  __syncthreads();
+  uint32_t pre = 0;
+  for (int i = 0; i < w; ++i) pre += sh4[i];
+  total = sh4[0] + sh4[1] + sh4[2] + sh4[3];
+  __syncthreads();
+  return pre + inc - x;
+}
+
+__device__ inline uint32_t block_sum(uint32_t x, uint32_t *sh4) {
+  uint32_t t;
+  block_excl_scan(x, sh4, t);
+  return t;
+}
+
+// Number of set bits of `mask` below the calling lane.
+__device__ inline int lanes_below(uint64_t mask) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// --------------------------------------------------------- projection ----
+
+// Record (pixel units) and tile rectangle of one projected Gaussian.
+__device__ inline Rec2 make_rec2(const Gauss &G, const Proj2 &P, const DevView &V,
+                                 const ProjArgs &a) {
+  Rec2 r;
+  r.r0 = 1u;  // empty rectangle: tx0 = 1 > tx1 = 0
+  r.r1 = 0u;
+  if (!P.ok) {
+    r.pu = r.pv = r.c00 = r.c01 = r.c11 = r.rho = 0.f;
+    return r;
+  }
+  r.pu = P.ph0 * V.inv_hu + V.cu;
+  r.pv = P.ph1 * V.inv_hv + V.cv;
+  r.c00 = -0.5f * kLog2e * P.A00 * V.hu * V.hu;
+  r.c01 = -kLog2e * P.A01 * V.hu * V.hv;
+  r.c11 = -0.5f * kLog2e * P.A11 * V.hv * V.hv;
+  r.rho = P.mu * G.rho;
+  float ru = a.kappa * sqrtf(P.S00) * V.inv_hu;
+  float rv = a.kappa * sqrtf(P.S11) * V.inv_hv;
+  const float eps = 1e-3f;
+  float x0 = fmaxf(ceilf(r.pu - ru - eps), 0.f);
+  float x1 = fminf(floorf(r.pu + ru + eps), (float)(a.width - 1));
+  float y0 = fmaxf(ceilf(r.pv - rv - eps), 0.f);
+  float y1 = fminf(floorf(r.pv + rv + eps), (float)(a.height - 1));
+  if (x0 <= x1 && y0 <= y1) {
+    int tx0 = (int)x0 / kTile, tx1 = (int)x1 / kTile;
+    int ty0 = (int)y0 / kTile, ty1 = (int)y1 / kTile;
+    r.r0 = (uint32_t)tx0 | ((uint32_t)ty0 << 16);
+    r.r1 = (uint32_t)tx1 | ((uint32_t)ty1 << 16);
+  }
+  return r;
+}
+
+// Grid (C chunks, V views).  Projects the chunk's Gaussians for one view,
+// writes their records and counts tile entries in an LDS histogram.
+__global__ __launch_bounds__(kBlock) void k_proj_hist(ProjArgs a, Rec2 *__restrict__ rec,
+                                                      uint32_t *__restrict__ hist,
+                                                      uint32_t *__restrict__ chunk_cnt,
+                                                      unsigned long long *skipped) {
+  extern __shared__ uint32_t sh[];
+  __shared__ uint32_t sh4[4];
+  const int c = blockIdx.x, v = blockIdx.y, tid = threadIdx.x;
+  for (int t = tid; t < a.T; t += kBlock) sh[t] = 0;
+  __syncthreads();
+  const DevView V = a.views[v];
+  uint32_t cnt = 0, skip = 0;
+  const int64_t g0 = (int64_t)c * kChunk;
+  for (int k = 0; k < kChunkPerThread; ++k) {
+    int64_t g = g0 + (int64_t)k * kBlock + tid;
+    if (g >= a.M) break;
+    Gauss G;
+    load_gauss(a.mean, a.scale, a.quat, a.dens, g, G);
+    Proj2 P;
+    project_one(G, V, P);
+    Rec2 r = make_rec2(G, P, V, a);
+    skip += P.ok ? 0u : 1u;
+    rec[(int64_t)v * a.M + g] = r;
+    Rect2 rc = unpack_rect(r.r0, r.r1);
+    int n = rect_count(rc);
+    cnt += (uint32_t)n;
+    for (int ty = rc.y0; ty <= rc.y1 && n; ++ty)
+      for (int tx = rc.x0; tx <= rc.x1; ++tx) atomicAdd(&sh[ty * a.TX + tx], 1u);
+  }
+  uint32_t tot = block_sum(cnt, sh4);
+  uint32_t sk = block_sum(skip, sh4);
+  __syncthreads();
+  uint32_t *h = hist + ((int64_t)v * a.C + c) * a.T;
+  for (int t = tid; t < a.T; t += kBlock) h[t] = sh[t];
+  if (tid == 0) {
+    chunk_cnt[v * a.C + c] = tot;
+    if (sk) atomicAdd(skipped, (unsigned long long)sk);
+  }
+}
+
+void launch_proj_hist(const ProjArgs &a, Rec2 *rec, uint32_t *hist, uint32_t *chunk_cnt,
+                      unsigned long long *skipped, hipStream_t s) {
+  dim3 grid(a.C, a.V);
+  hipLaunchKernelGGL(k_proj_hist, grid, dim3(kBlock), a.T * sizeof(uint32_t), s, a, rec, hist,
+                     chunk_cnt, skipped);
+}
+
+// Per (group, tile): exclusive prefix over chunks, in place; tile totals.
+__global__ __launch_bounds__(kBlock) void k_hist_colscan(int groups, int C, int T,
+                                                         uint32_t *__restrict__ hist,
+                                                         uint32_t *__restrict__ tile_total) {
+  int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= (int64_t)groups * T) return;
+  int grp = (int)(id / T), t = (int)(id - (int64_t)grp * T);
+  uint32_t run = 0;
+  for (int c = 0; c < C; ++c) {
+    int64_t idx = ((int64_t)grp * C + c) * T + t;
+    uint32_t x = hist[idx];
+    hist[idx] = run;
+    run += x;
+  }
+  tile_total[id] = run;
+}
+
+void launch_hist_colscan(int groups, int C, int T, uint32_t *hist, uint32_t *tile_total,
+                         hipStream_t s) {
+  int64_t n = (int64_t)groups * T;
+  hipLaunchKernelGGL(k_hist_colscan, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                     s, groups, C, T, hist, tile_total);
+}
+
+// Grid (C, V).  Writes each Gaussian's tile entries at its tiles' cursors and
+// the base index of its backward slots (Gaussian order within the chunk).
+__global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 *__restrict__ rec,
+                                                         const uint32_t *__restrict__ hist,
+                                                         const uint32_t *__restrict__ tile_start,
+                                                         const uint32_t *__restrict__ chunk_start,
+                                                         uint32_t *__restrict__ list,
+                                                         uint32_t *__restrict__ offsets) {
+  extern __shared__ uint32_t cur[];
+  __shared__ uint32_t sh4[4];
+  const int c = blockIdx.x, v = blockIdx.y, tid = threadIdx.x;
+  const uint32_t *h = hist + ((int64_t)v * a.C + c) * a.T;
+  const uint32_t *ts = tile_start + (int64_t)v * a.T;
+  for (int t = tid; t < a.T; t += kBlock) cur[t] = ts[t] + h[t];
+  __syncthreads();
+  uint32_t base = chunk_start[v * a.C + c];
+  const int64_t g0 = (int64_t)c * kChunk;
+  for (int k = 0; k < kChunkPerThread; ++k) {
+    int64_t gk = g0 + (int64_t)k * kBlock;
+    if (gk >= a.M) break;
+    int64_t g = gk + tid;
+    bool valid = g < a.M;
+    Rect2 rc{1, 0, 0, 0};
+    if (valid) {
+      const Rec2 &r = rec[(int64_t)v * a.M + g];
+      rc = unpack_rect(r.r0, r.r1);
+    }
+    int n = valid ? rect_count(rc) : 0;
+    uint32_t total;
+    uint32_t ex = block_excl_scan((uint32_t)n, sh4, total);
+    if (valid) offsets[(int64_t)v * a.M + g] = base + ex;
+    for (int ty = rc.y0; ty <= rc.y1 && n; ++ty)
+      for (int tx = rc.x0; tx <= rc.x1; ++tx) {
+        uint32_t pos = atomicAdd(&cur[ty * a.TX + tx], 1u);
+        list[pos] = (uint32_t)g;
+      }
+    base += total;
+  }
+}
+
+void launch_proj_scatter(const ProjArgs &a, const Rec2 *rec, const uint32_t *hist,
+                         const uint32_t *tile_start, const uint32_t *chunk_start, uint32_t *list,
+                         uint32_t *offsets, hipStream_t s) {
+  dim3 grid(a.C, a.V);
+  hipLaunchKernelGGL(k_proj_scatter, grid, dim3(kBlock), a.T * sizeof(uint32_t), s, a, rec, hist,
+                     tile_start, chunk_start, list, offsets);
+}
+
+// ------------------------------------------------------- render forward --
+
+// One workgroup per (view, 16x16 tile); wave w owns the 8x8 sub-tile
+// (w & 1, w >> 1), one pixel per lane.  The tile's records are staged in LDS
+// in batches of 256; each wave keeps, by ballot, only the records whose cutoff
+// ellipse meets its sub-tile, and sums rho_hat exp2(q') over them (a plain sum:
+// Eq. 7 composes 2D Gaussians additively, so the order is free).
+__global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *__restrict__ rec,
+                                                       const uint32_t *__restrict__ list,
+                                                       const uint32_t *__restrict__ tile_start,
+                                                       float *__restrict__ image) {
+  __shared__ float s_pu[kBlock], s_pv[kBlock], s_c00[kBlock], s_c01[kBlock], s_c11[kBlock];
+  __shared__ float s_rho[kBlock], s_ia[kBlock], s_ic[kBlock];
+  const int item = xcd_remap(blockIdx.x, gridDim.x);
+  const int v = item / a.T, t = item - v * a.T;
+  const int ty = t / a.TX, tx = t - ty * a.TX;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int sx0 = tx * kTile + (w & 1) * kSub, sy0 = ty * kTile + (w >> 1) * kSub;
+  const int px = sx0 + (lane & 7), py = sy0 + (lane >> 3);
+  const float fx = (float)px, fy = (float)py;
+  const float rx0 = (float)sx0, rx1 = (float)(sx0 + kSub - 1);
+  const float ry0 = (float)sy0, ry1 = (float)(sy0 + kSub - 1);
+  const uint32_t beg = tile_start[item], end = tile_start[item + 1];
+  const Rec2 *rv = rec + (int64_t)v * a.M;
+  float acc = 0.f;
+  for (uint32_t base = beg; base < end; base += kBlock) {
+    const int n = (int)min((uint32_t)kBlock, end - base);
+    __syncthreads();
+    if (tid < n) {
+      const uint32_t g = list[base + tid];
+      const float4 *p = reinterpret_cast<const float4 *>(rv + g);
+      float4 q0 = p[0], q1 = p[1];
+      s_pu[tid] = q0.x; s_pv[tid] = q0.y; s_c00[tid] = q0.z; s_c01[tid] = q0.w;
+      s_c11[tid] = q1.x; s_rho[tid] = q1.y;
+      s_ia[tid] = -0.5f / q0.z;
+      s_ic[tid] = -0.5f / q1.x;
+    }
+    __syncthreads();
+    for (int c0 = 0; c0 < n; c0 += 64) {
+      const int i = c0 + lane;
+      bool hit = false;
+      if (i < n) {
+        const float pu = s_pu[i], pv = s_pv[i];
+        float m = rect_min_form(-s_c00[i], -s_c01[i], -s_c11[i], s_ia[i], s_ic[i], rx0 - pu,
+                                rx1 - pu, ry0 - pv, ry1 - pv);
+        hit = m <= a.qmax;
+      }
+      uint64_t mask = __ballot(hit);
+      while (mask) {
+        const int e = c0 + __builtin_ctzll(mask);
+        mask &= mask - 1;
+        const float dx = fx - s_pu[e], dy = fy - s_pv[e];
+        const float q = dx * (s_c00[e] * dx + s_c01[e] * dy) + s_c11[e] * dy * dy;
+        const float ex = __builtin_amdgcn_exp2f(q);
+        acc += (q >= a.thr) ? s_rho[e] * ex : 0.f;
+      }
+    }
+  }
+  if (px < a.width && py < a.height) image[((int64_t)v * a.height + py) * a.width + px] = acc;
+}
+
+void launch_render_fwd(const ProjArgs &a, const Rec2 *rec, const uint32_t *list,
+                       const uint32_t *tile_start, float *image, hipStream_t s) {
+  int n = a.V * a.T;
+  hipLaunchKernelGGL(k_render_fwd, dim3(n), dim3(kBlock), 0, s, a, rec, list, tile_start, image);
+}
+
+// ------------------------------------------------------ render backward --
+
+// Same tiling as the forward.  For the upstream gradient G of one tile and
+// each (record, sub-tile) pair that the cutoff keeps, one lane walks the
+// sub-tile's 64 pixels and accumulates the moments
+//   S0 = sum G e, S1 = sum G e dx, S2 = sum G e dy,
+//   S3 = sum G e dx^2, S4 = sum G e dx dy, S5 = sum G e dy^2
+// (pixel units, e = exp2(q'), d = pixel - centre), which determine the
+// gradients with respect to rho_hat, the centre and the conic.  Lanes are
+// entries, so no cross-lane reduction is needed; the four waves' moments are
+// summed in a fixed order and written to the entry's slot (deterministic).
+__global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *__restrict__ rec,
+                                                       const uint32_t *__restrict__ list,
+                                                       const uint32_t *__restrict__ tile_start,
+                                                       const uint32_t *__restrict__ offsets,
+                                                       const float *__restrict__ grad_image,
+                                                       float *__restrict__ slots) {
+  __shared__ float s_pu[kBlock], s_pv[kBlock], s_c00[kBlock], s_c01[kBlock], s_c11[kBlock];
+  __shared__ float s_ia[kBlock], s_ic[kBlock];
+  __shared__ float s_G[kTile * kTile];
+  __shared__ float s_acc[4][6][kBlock];
+  __shared__ uint16_t s_q[4][kBlock];
+  const int item = xcd_remap(blockIdx.x, gridDim.x);
+  const int v = item / a.T, t = item - v * a.T;
+  const int ty = t / a.TX, tx = t - ty * a.TX;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int sxl = (w & 1) * kSub, syl = (w >> 1) * kSub;  // sub-tile origin within the tile
+  const int sx0 = tx * kTile + sxl, sy0 = ty * kTile + syl;
+  const float rx0 = (float)sx0, rx1 = (float)(sx0 + kSub - 1);
+  const float ry0 = (float)sy0, ry1 = (float)(sy0 + kSub - 1);
+  {
+    const int lx = tid & (kTile - 1), ly = tid / kTile;
+    const int gx = tx * kTile + lx, gy = ty * kTile + ly;
+    s_G[tid] = (gx < a.width && gy < a.height)
+                   ? grad_image[((int64_t)v * a.height + gy) * a.width + gx]
+                   : 0.f;
+  }
+  const uint32_t beg = tile_start[item], end = tile_start[item + 1];
+  const Rec2 *rv = rec + (int64_t)v * a.M;
+  const uint32_t *ov = offsets + (int64_t)v * a.M;
+  for (uint32_t base = beg; base < end; base += kBlock) {
+    const int n = (int)min((uint32_t)kBlock, end - base);
+    __syncthreads();
+    uint32_t my_slot = 0;
+    if (tid < n) {
+      const uint32_t g = list[base + tid];
+      const float4 *p = reinterpret_cast<const float4 *>(rv + g);
+      float4 q0 = p[0], q1 = p[1];
+      s_pu[tid] = q0.x; s_pv[tid] = q0.y; s_c00[tid] = q0.z; s_c01[tid] = q0.w;
+      s_c11[tid] = q1.x;
+      s_ia[tid] = -0.5f / q0.z;
+      s_ic[tid] = -0.5f / q1.x;
+      Rect2 rc = unpack_rect(__float_as_uint(q1.z), __float_as_uint(q1.w));
+      my_slot = ov[g] + (uint32_t)((ty - rc.y0) * (rc.x1 - rc.x0 + 1) + (tx - rc.x0));
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+#pragma unroll
+      for (int ww = 0; ww < 4; ++ww) s_acc[ww][k][tid] = 0.f;
+    __syncthreads();
+    // compact the records that meet this wave's sub-tile
+    int qn = 0;
+    for (int c0 = 0; c0 < n; c0 += 64) {
+      const int i = c0 + lane;
+      bool hit = false;
+      if (i < n) {
+        const float pu = s_pu[i], pv = s_pv[i];
+        float m = rect_min_form(-s_c00[i], -s_c01[i], -s_c11[i], s_ia[i], s_ic[i], rx0 - pu,
+                                rx1 - pu, ry0 - pv, ry1 - pv);
+        hit = m <= a.qmax;
+      }
+      uint64_t mask = __ballot(hit);
+      if (hit) s_q[w][qn + lanes_below(mask)] = (uint16_t)i;
+      qn += __popcll(mask);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int qb = 0; qb < qn; qb += 64) {
+      const int j = qb + lane;
+      const bool active = j < qn;
+      const int e = active ? (int)s_q[w][j] : 0;
+      const float pu = s_pu[e], pv = s_pv[e];
+      const float c00 = s_c00[e], c01 = s_c01[e], c11 = s_c11[e];
+      const float dd = 2.f * c00;
+      float S0 = 0.f, S1 = 0.f, S2 = 0.f, S3 = 0.f, S4 = 0.f, S5 = 0.f;
+      const float dx0 = rx0 - pu;
+#pragma unroll 2
+      for (int r = 0; r < kSub; ++r) {
+        const float dy = ry0 + (float)r - pv;
+        float dx = dx0;
+        float q = dx * (c00 * dx + c01 * dy) + c11 * dy * dy;
+        float d = c00 * (2.f * dx + 1.f) + c01 * dy;
+        float R0 = 0.f, R1 = 0.f, R3 = 0.f;
+        const float *Grow = s_G + (syl + r) * kTile + sxl;
+#pragma unroll
+        for (int col = 0; col < kSub; ++col) {
+          const float ex = __builtin_amdgcn_exp2f(q);
+          const float ge = (q >= a.thr) ? Grow[col] * ex : 0.f;
+          R0 += ge;
+          const float tt = ge * dx;
+          R1 += tt;
+          R3 = fmaf(tt, dx, R3);
+          q += d;
+          d += dd;
+          dx += 1.f;
+        }
+        S0 += R0;
+        S1 += R1;
+        S2 = fmaf(R0, dy, S2);
+        S3 += R3;
+        S4 = fmaf(R1, dy, S4);
+        S5 = fmaf(R0 * dy, dy, S5);
+      }
+      if (active) {
+        s_acc[w][0][e] = S0; s_acc[w][1][e] = S1; s_acc[w][2][e] = S2;
+        s_acc[w][3][e] = S3; s_acc[w][4][e] = S4; s_acc[w][5][e] = S5;
+      }
+    }
+    __syncthreads();
+    if (tid < n) {
+      float *o = slots + (int64_t)my_slot * 6;
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        o[k] = ((s_acc[0][k][tid] + s_acc[1][k][tid]) + s_acc[2][k][tid]) + s_acc[3][k][tid];
+    }
+  }
+}
+
+void launch_render_bwd(const ProjArgs &a, const Rec2 *rec, const uint32_t *list,
+                       const uint32_t *tile_start, const uint32_t *offsets, const float *grad_image,
+                       float *slots, hipStream_t s) {
+  int n = a.V * a.T;
+  hipLaunchKernelGGL(k_render_bwd, dim3(n), dim3(kBlock), 0, s, a, rec, list, tile_start, offsets,
+                     grad_image, slots);
+}
+
+// ------------------------------------------------- per-Gaussian chain rule --
+
+// One thread per Gaussian, looping over views in order (deterministic): sums
+// the moments of its tile slots, converts them to the gradients of rho_hat,
+// the projected centre and the conic, and applies the chain rule through the
+// inverse, Sigma_hat = B B^T with B = J W R S, the rectification factor
+// mu = sqrt(2 pi / (d^T Sigma^{-1} d)), the perspective Jacobian J(t), the
+// perspective division and t = W p + t0.
+__global__ __launch_bounds__(kBlock) void k_proj_chain(ProjArgs a, const Rec2 *__restrict__ rec,
+                                                       const uint32_t *__restrict__ offsets,
+                                                       const float *__restrict__ slots,
+                                                       float *g_mean, float *g_scale, float *g_quat,
+                                                       float *g_dens, int accumulate) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= a.M) return;
+  Gauss G;
+  load_gauss(a.mean, a.scale, a.quat, a.dens, g, G);
+  float gp[3] = {0.f, 0.f, 0.f}, gs[3] = {0.f, 0.f, 0.f}, gR[9] = {0.f};
+  float grho = 0.f;
+  if (G.ok) {
+    for (int v = 0; v < a.V; ++v) {
+      const int64_t vg = (int64_t)v * a.M + g;
+      const Rec2 r = rec[vg];
+      const Rect2 rc = unpack_rect(r.r0, r.r1);
+      const int cnt = rect_count(rc);
+      if (!cnt) continue;
+      const float *sl = slots + (int64_t)offsets[vg] * 6;
+      float S[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      for (int k = 0; k < cnt; ++k)
+#pragma unroll
+        for (int j = 0; j < 6; ++j) S[j] += sl[6 * k + j];
+      const DevView V = a.views[v];
+      Proj2 P;
+      project_one(G, V, P);
+      const float rh = P.mu * G.rho;
+      // world-unit moments
+      const float T1 = S[1] * V.hu, T2 = S[2] * V.hv;
+      const float T3 = S[3] * V.hu * V.hu, T4 = S[4] * V.hu * V.hv, T5 = S[5] * V.hv * V.hv;
+      const float g_rh = S[0];
+      const float gph0 = rh * (P.A00 * T1 + P.A01 * T2);
+      const float gph1 = rh * (P.A01 * T1 + P.A11 * T2);
+      // dL/dA as a symmetric matrix (each entry), then dL/dSigma_hat = -A Gb A
+      const float Gb00 = -0.5f * rh * T3, Gb01 = -0.5f * rh * T4, Gb11 = -0.5f * rh * T5;
+      const float X00 = P.A00 * Gb00 + P.A01 * Gb01, X01 = P.A00 * Gb01 + P.A01 * Gb11;
+      const float X10 = P.A01 * Gb00 + P.A11 * Gb01, X11 = P.A01 * Gb01 + P.A11 * Gb11;
+      const float gS00 = -(X00 * P.A00 + X01 * P.A01);
+      const float gS01 = -0.5f * ((X00 * P.A01 + X01 * P.A11) + (X10 * P.A00 + X11 * P.A01));
+      const float gS11 = -(X10 * P.A01 + X11 * P.A11);
+      // Sigma_hat = B B^T
+      float gB[6];
+      for (int j = 0; j < 3; ++j) {
+        gB[j] = 2.f * (gS00 * P.B[j] + gS01 * P.B[3 + j]);
+        gB[3 + j] = 2.f * (gS01 * P.B[j] + gS11 * P.B[3 + j]);
+      }
+      // B = JW M
+      float gJW[6];
+      for (int aa = 0; aa < 2; ++aa)
+        for (int i = 0; i < 3; ++i)
+          gJW[3 * aa + i] = gB[3 * aa] * P.M[3 * i] + gB[3 * aa + 1] * P.M[3 * i + 1] +
+                            gB[3 * aa + 2] * P.M[3 * i + 2];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          const float gM = P.JW[i] * gB[j] + P.JW[3 + i] * gB[3 + j];
+          gR[3 * i + j] += gM * G.s[j];
+          gs[j] += gM * G.R[3 * i + j];
+        }
+      // rho_hat = mu rho,  mu = sqrt(2 pi / m),  m = sum_j (r_j / s_j)^2,  r = R^T d
+      grho += P.mu * g_rh;
+      const float gmu = G.rho * g_rh;
+      const float gm = gmu * (-0.5f * P.mu / P.m);
+      float gd[3] = {0.f, 0.f, 0.f};
+      for (int j = 0; j < 3; ++j) {
+        const float is2 = 1.f / (G.s[j] * G.s[j]);
+        const float gr = gm * 2.f * P.r[j] * is2;
+        gs[j] += gm * (-2.f * P.r[j] * P.r[j] * is2 / G.s[j]);
+        for (int i = 0; i < 3; ++i) {
+          gR[3 * i + j] += P.d[i] * gr;
+          gd[i] += G.R[3 * i + j] * gr;
+        }
+      }
+      float gt[3] = {0.f, 0.f, 0.f};
+      const float *W = V.W;
+      if (V.beam == 1) {
+        // d = W^T u, u = t / |t|
+        float gu[3];
+        for (int aa = 0; aa < 3; ++aa)
+          gu[aa] = W[3 * aa] * gd[0] + W[3 * aa + 1] * gd[1] + W[3 * aa + 2] * gd[2];
+        const float ug = P.u[0] * gu[0] + P.u[1] * gu[1] + P.u[2] * gu[2];
+        const float il = 1.f / P.l;
+        for (int aa = 0; aa < 3; ++aa) gt[aa] += (gu[aa] - P.u[aa] * ug) * il;
+        // JW = J2 W
+        float gJ[6];
+        for (int aa = 0; aa < 2; ++aa)
+          for (int k = 0; k < 3; ++k)
+            gJ[3 * aa + k] = gJW[3 * aa] * W[3 * k] + gJW[3 * aa + 1] * W[3 * k + 1] +
+                             gJW[3 * aa + 2] * W[3 * k + 2];
+        const float L = V.L_SD, t0 = P.t[0], t1 = P.t[1], inv = 1.f / P.t[2];
+        const float Li2 = L * inv * inv;
+        gt[0] += -gJ[2] * Li2;
+        gt[1] += -gJ[5] * Li2;
+        gt[2] += -(gJ[0] + gJ[4]) * Li2 + (gJ[2] * t0 + gJ[5] * t1) * 2.f * Li2 * inv;
+        // p_hat = L (t0, t1) / t2
+        gt[0] += L * inv * gph0;
+        gt[1] += L * inv * gph1;
+        gt[2] += -Li2 * (t0 * gph0 + t1 * gph1);
+      } else {
+        gt[0] += gph0;
+        gt[1] += gph1;
+      }
+      for (int i = 0; i < 3; ++i) gp[i] += W[i] * gt[0] + W[3 + i] * gt[1] + W[6 + i] * gt[2];
+    }
+  }
+  float gq[4] = {0.f, 0.f, 0.f, 0.f};
+  if (G.ok) quat_backward(G, gR, gq);
+  if (g_mean)
+    for (int i = 0; i < 3; ++i) g_mean[3 * g + i] = accumulate ? g_mean[3 * g + i] + gp[i] : gp[i];
+  if (g_scale)
+    for (int i = 0; i < 3; ++i)
+      g_scale[3 * g + i] = accumulate ? g_scale[3 * g + i] + gs[i] : gs[i];
+  if (g_quat)
+    for (int i = 0; i < 4; ++i) g_quat[4 * g + i] = accumulate ? g_quat[4 * g + i] + gq[i] : gq[i];
+  if (g_dens) g_dens[g] = accumulate ? g_dens[g] + grho : grho;
+}
+
+void launch_proj_chain(const ProjArgs &a, const Rec2 *rec, const uint32_t *offsets,
+                       const float *slots, float *g_mean, float *g_scale, float *g_quat,
+                       float *g_dens, int accumulate, hipStream_t s) {
+  unsigned nb = (unsigned)((a.M + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_proj_chain, dim3(nb), dim3(kBlock), 0, s, a, rec, offsets, slots, g_mean,
+                     g_scale, g_quat, g_dens, accumulate);
+}
+
+}  // namespace gsk

@@ -1,0 +1,431 @@
+// Voxelizer kernels (paper Sec. 3.2.2, Eq. 3-4): per-Gaussian records with 3D
+// tile boxes, per-group LDS tile histograms, tile-list scatter, 8^3-tile
+// forward and backward, and the per-Gaussian chain rule.
+#include "internal.h"
+
+namespace gsk {
+
+__device__ inline uint32_t pack16(int lo, int hi) { return (uint32_t)lo | ((uint32_t)hi << 16); }
+
+// One thread per Gaussian: precision matrix P = R S^-2 R^T, centre and conic
+// in voxel-index units, cutoff bounding box and its 8^3-tile box.
+__global__ __launch_bounds__(kBlock) void k_vox_records(VoxArgs a, Rec3 *__restrict__ rec,
+                                                        uint32_t *__restrict__ count,
+                                                        unsigned long long *skipped) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= a.M) return;
+  Gauss G;
+  load_gauss(a.mean, a.scale, a.quat, a.dens, g, G);
+  Rec3 r;
+  r.t0 = pack16(1, 0);  // empty box: tx0 = 1 > tx1 = 0
+  r.t1 = pack16(0, 0);
+  r.t2 = pack16(0, 0);
+  float P[9], Sd[3];
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j) {
+      float acc = 0.f;
+      for (int k = 0; k < 3; ++k) acc += G.R[3 * i + k] * G.R[3 * j + k] / (G.s[k] * G.s[k]);
+      P[3 * i + j] = acc;
+    }
+    float sd = 0.f;
+    for (int k = 0; k < 3; ++k) sd += G.R[3 * i + k] * G.R[3 * i + k] * G.s[k] * G.s[k];
+    Sd[i] = sd;
+  }
+  const float *h = a.spacing;
+  const int n[3] = {a.nx, a.ny, a.nz};
+  bool ok = G.ok;
+  for (int i = 0; i < 9; ++i) ok = ok && finitef(P[i]);
+  int lo[3], hi[3];
+  for (int i = 0; i < 3; ++i) {
+    r.c[i] = (G.p[i] - a.origin[i]) / h[i] - 0.5f;
+    float rad = a.kappa * sqrtf(Sd[i]) / h[i];
+    (&r.rx)[i] = rad;
+    float l = fmaxf(ceilf(r.c[i] - rad - 1e-3f), 0.f);
+    float u = fminf(floorf(r.c[i] + rad + 1e-3f), (float)(n[i] - 1));
+    if (!(l <= u)) ok = false;
+    lo[i] = ok ? (int)l : 0;
+    hi[i] = ok ? (int)u : 0;
+  }
+  const float s = -0.5f * kLog2e;
+  r.c00 = s * P[0] * h[0] * h[0];
+  r.c01 = 2.f * s * P[1] * h[0] * h[1];
+  r.c02 = 2.f * s * P[2] * h[0] * h[2];
+  r.c11 = s * P[4] * h[1] * h[1];
+  r.c12 = 2.f * s * P[5] * h[1] * h[2];
+  r.c22 = s * P[8] * h[2] * h[2];
+  r.rho = G.rho;
+  uint32_t cnt = 0;
+  if (ok) {
+    int tx0 = lo[0] / kVTile, ty0 = lo[1] / kVTile, tz0 = lo[2] / kVTile;
+    int tx1 = hi[0] / kVTile, ty1 = hi[1] / kVTile, tz1 = hi[2] / kVTile;
+    r.t0 = pack16(tx0, ty0);
+    r.t1 = pack16(tz0, tx1);
+    r.t2 = pack16(ty1, tz1);
+    cnt = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1) * (tz1 - tz0 + 1));
+  } else {
+    r.rho = 0.f;
+  }
+  rec[g] = r;
+  count[g] = cnt;
+  if (!G.ok) atomicAdd(skipped, 1ull);
+}
+
+void launch_vox_records(const VoxArgs &a, Rec3 *rec, uint32_t *count, unsigned long long *skipped,
+                        hipStream_t s) {
+  unsigned nb = (unsigned)((a.M + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_vox_records, dim3(nb), dim3(kBlock), 0, s, a, rec, count, skipped);
+}
+
+// Tile index of (tx, ty, tz) within its group, the group owning z tile layers
+// [grp * layers, (grp + 1) * layers).
+__device__ inline int group_tile(const VoxArgs &a, int grp, int tx, int ty, int tz) {
+  return ((tz - grp * a.layers) * a.TY + ty) * a.TX + tx;
+}
+
+// Grid (C, G): LDS histogram of the chunk's tile entries within one group.
+__global__ __launch_bounds__(kBlock) void k_vox_hist(VoxArgs a, const Rec3 *__restrict__ rec,
+                                                     uint32_t *__restrict__ hist) {
+  extern __shared__ uint32_t sh[];
+  const int c = blockIdx.x, grp = blockIdx.y, tid = threadIdx.x;
+  for (int t = tid; t < a.Tg; t += kBlock) sh[t] = 0;
+  __syncthreads();
+  const int zl = grp * a.layers, zh = min(zl + a.layers, a.TZ) - 1;
+  const int64_t g0 = (int64_t)c * kChunk;
+  for (int k = 0; k < kChunkPerThread; ++k) {
+    int64_t g = g0 + (int64_t)k * kBlock + tid;
+    if (g >= a.M) break;
+    Box3 b = unpack_box(rec[g]);
+    if (!box_count(b)) continue;
+    int z0 = max(b.z0, zl), z1 = min(b.z1, zh);
+    for (int tz = z0; tz <= z1; ++tz)
+      for (int ty = b.y0; ty <= b.y1; ++ty)
+        for (int tx = b.x0; tx <= b.x1; ++tx) atomicAdd(&sh[group_tile(a, grp, tx, ty, tz)], 1u);
+  }
+  __syncthreads();
+  uint32_t *hp = hist + ((int64_t)grp * a.C + c) * a.Tg;
+  for (int t = tid; t < a.Tg; t += kBlock) hp[t] = sh[t];
+}
+
+void launch_vox_hist(const VoxArgs &a, const Rec3 *rec, uint32_t *hist, hipStream_t s) {
+  hipLaunchKernelGGL(k_vox_hist, dim3(a.C, a.G), dim3(kBlock), a.Tg * sizeof(uint32_t), s, a, rec,
+                     hist);
+}
+
+__global__ __launch_bounds__(kBlock) void k_vox_scatter(VoxArgs a, const Rec3 *__restrict__ rec,
+                                                        const uint32_t *__restrict__ hist,
+                                                        const uint32_t *__restrict__ tile_start,
+                                                        uint32_t *__restrict__ list) {
+  extern __shared__ uint32_t cur[];
+  const int c = blockIdx.x, grp = blockIdx.y, tid = threadIdx.x;
+  const uint32_t *hp = hist + ((int64_t)grp * a.C + c) * a.Tg;
+  const uint32_t *ts = tile_start + (int64_t)grp * a.Tg;
+  for (int t = tid; t < a.Tg; t += kBlock) cur[t] = ts[t] + hp[t];
+  __syncthreads();
+  const int zl = grp * a.layers, zh = min(zl + a.layers, a.TZ) - 1;
+  const int64_t g0 = (int64_t)c * kChunk;
+  for (int k = 0; k < kChunkPerThread; ++k) {
+    int64_t g = g0 + (int64_t)k * kBlock + tid;
+    if (g >= a.M) break;
+    Box3 b = unpack_box(rec[g]);
+    if (!box_count(b)) continue;
+    int z0 = max(b.z0, zl), z1 = min(b.z1, zh);
+    for (int tz = z0; tz <= z1; ++tz)
+      for (int ty = b.y0; ty <= b.y1; ++ty)
+        for (int tx = b.x0; tx <= b.x1; ++tx) {
+          uint32_t pos = atomicAdd(&cur[group_tile(a, grp, tx, ty, tz)], 1u);
+          list[pos] = (uint32_t)g;
+        }
+  }
+}
+
+void launch_vox_scatter(const VoxArgs &a, const Rec3 *rec, const uint32_t *hist,
+                        const uint32_t *tile_start, uint32_t *list, hipStream_t s) {
+  hipLaunchKernelGGL(k_vox_scatter, dim3(a.C, a.G), dim3(kBlock), a.Tg * sizeof(uint32_t), s, a,
+                     rec, hist, tile_start, list);
+}
+
+// --------------------------------------------------------------- forward --
+
+struct VoxTile {
+  int tx, ty, tz;
+  bool valid;
+};
+
+__device__ inline VoxTile decode_item(const VoxArgs &a, int item) {
+  VoxTile r;
+  int grp = item / a.Tg, within = item - grp * a.Tg;
+  int plane = a.TX * a.TY;
+  int lz = within / plane, rem = within - lz * plane;
+  r.ty = rem / a.TX;
+  r.tx = rem - r.ty * a.TX;
+  r.tz = grp * a.layers + lz;
+  r.valid = r.tz < a.TZ;
+  return r;
+}
+
+// Stage one batch of records in LDS (13 floats each, structure of arrays).
+__device__ inline void stage_rec3(const Rec3 &r, float (*s)[kBlock], int tid) {
+  s[0][tid] = r.c[0]; s[1][tid] = r.c[1]; s[2][tid] = r.c[2];
+  s[3][tid] = r.c00; s[4][tid] = r.c01; s[5][tid] = r.c02;
+  s[6][tid] = r.c11; s[7][tid] = r.c12; s[8][tid] = r.c22;
+  s[9][tid] = r.rho;
+  s[10][tid] = r.rx; s[11][tid] = r.ry; s[12][tid] = r.rz;
+}
+
+__device__ inline bool box_hits(const float (*s)[kBlock], int i, float x0, float y0, float z0) {
+  const float e = (float)(kVSub - 1);
+  const float cx = s[0][i], cy = s[1][i], cz = s[2][i];
+  const float rx = s[10][i], ry = s[11][i], rz = s[12][i];
+  return (cx + rx >= x0) && (cx - rx <= x0 + e) && (cy + ry >= y0) && (cy - ry <= y0 + e) &&
+         (cz + rz >= z0) && (cz - rz <= z0 + e);
+}
+
+__device__ inline float vox_q(const float (*s)[kBlock], int e, float dx, float dy, float dz) {
+  return dx * (s[3][e] * dx + s[4][e] * dy + s[5][e] * dz) + dy * (s[6][e] * dy + s[7][e] * dz) +
+         s[8][e] * dz * dz;
+}
+
+// One workgroup per 8^3 tile; wave w owns the 4^3 sub-cubes w and w + 4,
+// one voxel per lane; ballot-culled records from an LDS batch.
+__global__ __launch_bounds__(kBlock) void k_vox_fwd(VoxArgs a, const Rec3 *__restrict__ rec,
+                                                    const uint32_t *__restrict__ list,
+                                                    const uint32_t *__restrict__ tile_start,
+                                                    float *__restrict__ vol) {
+  __shared__ float s[13][kBlock];
+  const int item = xcd_remap(blockIdx.x, gridDim.x);
+  const VoxTile T = decode_item(a, item);
+  if (!T.valid) return;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  float acc[2] = {0.f, 0.f};
+  int vx[2], vy[2], vz[2];
+  float ox[2], oy[2], oz[2];
+  for (int k = 0; k < 2; ++k) {
+    const int sc = w + 4 * k;
+    ox[k] = (float)(T.tx * kVTile + (sc & 1) * kVSub);
+    oy[k] = (float)(T.ty * kVTile + ((sc >> 1) & 1) * kVSub);
+    oz[k] = (float)(T.tz * kVTile + (sc >> 2) * kVSub);
+    vx[k] = (int)ox[k] + (lane & 3);
+    vy[k] = (int)oy[k] + ((lane >> 2) & 3);
+    vz[k] = (int)oz[k] + (lane >> 4);
+  }
+  const uint32_t beg = tile_start[item], end = tile_start[item + 1];
+  for (uint32_t base = beg; base < end; base += kBlock) {
+    const int n = (int)min((uint32_t)kBlock, end - base);
+    __syncthreads();
+    if (tid < n) stage_rec3(rec[list[base + tid]], s, tid);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      for (int c0 = 0; c0 < n; c0 += 64) {
+        const int i = c0 + lane;
+        const bool hit = (i < n) && box_hits(s, i, ox[k], oy[k], oz[k]);
+        uint64_t mask = __ballot(hit);
+        while (mask) {
+          const int e = c0 + __builtin_ctzll(mask);
+          mask &= mask - 1;
+          const float q = vox_q(s, e, (float)vx[k] - s[0][e], (float)vy[k] - s[1][e],
+                                (float)vz[k] - s[2][e]);
+          const float ex = __builtin_amdgcn_exp2f(q);
+          acc[k] += (q >= a.thr) ? s[9][e] * ex : 0.f;
+        }
+      }
+    }
+  }
+  for (int k = 0; k < 2; ++k)
+    if (vx[k] < a.nx && vy[k] < a.ny && vz[k] < a.nz)
+      vol[((int64_t)vz[k] * a.ny + vy[k]) * a.nx + vx[k]] = acc[k];
+}
+
+void launch_vox_fwd(const VoxArgs &a, const Rec3 *rec, const uint32_t *list,
+                    const uint32_t *tile_start, float *volume, hipStream_t s) {
+  int n = a.G * a.Tg;
+  hipLaunchKernelGGL(k_vox_fwd, dim3(n), dim3(kBlock), 0, s, a, rec, list, tile_start, volume);
+}
+
+// -------------------------------------------------------------- backward --
+
+// Lanes are (record, sub-cube) pairs; each walks the sub-cube's 64 voxels and
+// accumulates 10 moments of H e (e = exp2(q')): 1, d_i, d_i d_j (index units,
+// d = voxel - centre).  Per-wave LDS accumulators, summed in fixed order.
+__global__ __launch_bounds__(kBlock) void k_vox_bwd(VoxArgs a, const Rec3 *__restrict__ rec,
+                                                    const uint32_t *__restrict__ list,
+                                                    const uint32_t *__restrict__ tile_start,
+                                                    const uint32_t *__restrict__ offsets,
+                                                    const float *__restrict__ grad_vol,
+                                                    float *__restrict__ slots) {
+  __shared__ float s[13][kBlock];
+  __shared__ float s_H[kVTile * kVTile * kVTile];
+  __shared__ float s_acc[4][10][kBlock];
+  __shared__ uint16_t s_q[4][kBlock];
+  const int item = xcd_remap(blockIdx.x, gridDim.x);
+  const VoxTile T = decode_item(a, item);
+  if (!T.valid) return;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int i = tid; i < kVTile * kVTile * kVTile; i += kBlock) {
+    const int lx = i & 7, ly = (i >> 3) & 7, lz = i >> 6;
+    const int x = T.tx * kVTile + lx, y = T.ty * kVTile + ly, z = T.tz * kVTile + lz;
+    s_H[i] = (x < a.nx && y < a.ny && z < a.nz) ? grad_vol[((int64_t)z * a.ny + y) * a.nx + x] : 0.f;
+  }
+  const uint32_t beg = tile_start[item], end = tile_start[item + 1];
+  for (uint32_t base = beg; base < end; base += kBlock) {
+    const int n = (int)min((uint32_t)kBlock, end - base);
+    __syncthreads();
+    uint32_t my_slot = 0;
+    if (tid < n) {
+      const uint32_t g = list[base + tid];
+      const Rec3 r = rec[g];
+      stage_rec3(r, s, tid);
+      const Box3 b = unpack_box(r);
+      const int bx = b.x1 - b.x0 + 1, by = b.y1 - b.y0 + 1;
+      my_slot = offsets[g] + (uint32_t)(((T.tz - b.z0) * by + (T.ty - b.y0)) * bx + (T.tx - b.x0));
+    }
+    for (int k = 0; k < 10; ++k)
+      for (int ww = 0; ww < 4; ++ww) s_acc[ww][k][tid] = 0.f;
+    __syncthreads();
+    for (int kk = 0; kk < 2; ++kk) {
+      const int sc = w + 4 * kk;
+      const int lx0 = (sc & 1) * kVSub, ly0 = ((sc >> 1) & 1) * kVSub, lz0 = (sc >> 2) * kVSub;
+      const float ox = (float)(T.tx * kVTile + lx0), oy = (float)(T.ty * kVTile + ly0),
+                  oz = (float)(T.tz * kVTile + lz0);
+      int qn = 0;
+      for (int c0 = 0; c0 < n; c0 += 64) {
+        const int i = c0 + lane;
+        const bool hit = (i < n) && box_hits(s, i, ox, oy, oz);
+        uint64_t mask = __ballot(hit);
+        if (hit)
+          s_q[w][qn + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u))] =
+              (uint16_t)i;
+        qn += __popcll(mask);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int qb = 0; qb < qn; qb += 64) {
+        const int j = qb + lane;
+        const bool active = j < qn;
+        const int e = active ? (int)s_q[w][j] : 0;
+        float m[10];
+        for (int k = 0; k < 10; ++k) m[k] = 0.f;
+        const float cx = s[0][e], cy = s[1][e], cz = s[2][e];
+        for (int z = 0; z < kVSub; ++z) {
+          const float dz = oz + (float)z - cz;
+          for (int y = 0; y < kVSub; ++y) {
+            const float dy = oy + (float)y - cy;
+            const float *Hrow = s_H + ((lz0 + z) * kVTile + (ly0 + y)) * kVTile + lx0;
+#pragma unroll
+            for (int x = 0; x < kVSub; ++x) {
+              const float dx = ox + (float)x - cx;
+              const float q = vox_q(s, e, dx, dy, dz);
+              const float ex = __builtin_amdgcn_exp2f(q);
+              const float he = (q >= a.thr) ? Hrow[x] * ex : 0.f;
+              m[0] += he;
+              m[1] = fmaf(he, dx, m[1]);
+              m[2] = fmaf(he, dy, m[2]);
+              m[3] = fmaf(he, dz, m[3]);
+              const float hx = he * dx, hy = he * dy;
+              m[4] = fmaf(hx, dx, m[4]);
+              m[5] = fmaf(hx, dy, m[5]);
+              m[6] = fmaf(hx, dz, m[6]);
+              m[7] = fmaf(hy, dy, m[7]);
+              m[8] = fmaf(hy, dz, m[8]);
+              m[9] = fmaf(he * dz, dz, m[9]);
+            }
+          }
+        }
+        if (active)
+          for (int k = 0; k < 10; ++k) s_acc[w][k][e] += m[k];
+      }
+    }
+    __syncthreads();
+    if (tid < n) {
+      float *o = slots + (int64_t)my_slot * 10;
+      for (int k = 0; k < 10; ++k)
+        o[k] = ((s_acc[0][k][tid] + s_acc[1][k][tid]) + s_acc[2][k][tid]) + s_acc[3][k][tid];
+    }
+  }
+}
+
+void launch_vox_bwd(const VoxArgs &a, const Rec3 *rec, const uint32_t *list,
+                    const uint32_t *tile_start, const uint32_t *offsets, const float *grad_volume,
+                    float *slots, hipStream_t s) {
+  int n = a.G * a.Tg;
+  hipLaunchKernelGGL(k_vox_bwd, dim3(n), dim3(kBlock), 0, s, a, rec, list, tile_start, offsets,
+                     grad_volume, slots);
+}
+
+// One thread per Gaussian: sum the tile slots' moments and apply the chain
+// rule through the index-unit conic, P = R S^-2 R^T and the quaternion.
+__global__ __launch_bounds__(kBlock) void k_vox_chain(VoxArgs a, const Rec3 *__restrict__ rec,
+                                                      const uint32_t *__restrict__ offsets,
+                                                      const float *__restrict__ slots,
+                                                      float *g_mean, float *g_scale, float *g_quat,
+                                                      float *g_dens, int accumulate) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= a.M) return;
+  Gauss G;
+  load_gauss(a.mean, a.scale, a.quat, a.dens, g, G);
+  float gp[3] = {0.f, 0.f, 0.f}, gs[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f};
+  float grho = 0.f;
+  const Rec3 r = rec[g];
+  const int cnt = box_count(unpack_box(r));
+  if (G.ok && cnt) {
+    float S[10];
+    for (int k = 0; k < 10; ++k) S[k] = 0.f;
+    const float *sl = slots + (int64_t)offsets[g] * 10;
+    for (int i = 0; i < cnt; ++i)
+      for (int k = 0; k < 10; ++k) S[k] += sl[10 * i + k];
+    const float *h = a.spacing;
+    // world-unit moments
+    const float T[3] = {S[1] * h[0], S[2] * h[1], S[3] * h[2]};
+    float Tm[9];
+    Tm[0] = S[4] * h[0] * h[0]; Tm[1] = S[5] * h[0] * h[1]; Tm[2] = S[6] * h[0] * h[2];
+    Tm[4] = S[7] * h[1] * h[1]; Tm[5] = S[8] * h[1] * h[2]; Tm[8] = S[9] * h[2] * h[2];
+    Tm[3] = Tm[1]; Tm[6] = Tm[2]; Tm[7] = Tm[5];
+    float P[9], is2[3];
+    for (int k = 0; k < 3; ++k) is2[k] = 1.f / (G.s[k] * G.s[k]);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        float acc = 0.f;
+        for (int k = 0; k < 3; ++k) acc += G.R[3 * i + k] * G.R[3 * j + k] * is2[k];
+        P[3 * i + j] = acc;
+      }
+    grho = S[0];
+    for (int i = 0; i < 3; ++i) gp[i] = G.rho * (P[3 * i] * T[0] + P[3 * i + 1] * T[1] + P[3 * i + 2] * T[2]);
+    // dL/dP (each entry) = -rho/2 Tm;  P = R D R^T, D = diag(s^-2)
+    float GP[9];
+    for (int i = 0; i < 9; ++i) GP[i] = -0.5f * G.rho * Tm[i];
+    float gR[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        float acc = 0.f;
+        for (int k = 0; k < 3; ++k) acc += GP[3 * i + k] * G.R[3 * k + j];
+        gR[3 * i + j] = 2.f * acc * is2[j];
+      }
+    for (int j = 0; j < 3; ++j) {
+      float acc = 0.f;
+      for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) acc += G.R[3 * i + j] * GP[3 * i + k] * G.R[3 * k + j];
+      gs[j] = -2.f * acc * is2[j] / G.s[j];
+    }
+    quat_backward(G, gR, gq);
+  }
+  if (g_mean)
+    for (int i = 0; i < 3; ++i) g_mean[3 * g + i] = accumulate ? g_mean[3 * g + i] + gp[i] : gp[i];
+  if (g_scale)
+    for (int i = 0; i < 3; ++i)
+      g_scale[3 * g + i] = accumulate ? g_scale[3 * g + i] + gs[i] : gs[i];
+  if (g_quat)
+    for (int i = 0; i < 4; ++i) g_quat[4 * g + i] = accumulate ? g_quat[4 * g + i] + gq[i] : gq[i];
+  if (g_dens) g_dens[g] = accumulate ? g_dens[g] + grho : grho;
+}
+
+void launch_vox_chain(const VoxArgs &a, const Rec3 *rec, const uint32_t *offsets,
+                      const float *slots, float *g_mean, float *g_scale, float *g_quat,
+                      float *g_dens, int accumulate, hipStream_t s) {
+  unsigned nb = (unsigned)((a.M + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_vox_chain, dim3(nb), dim3(kBlock), 0, s, a, rec, offsets, slots, g_mean,
+                     g_scale, g_quat, g_dens, accumulate);
+}
+
+}  // namespace gsk

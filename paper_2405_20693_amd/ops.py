@@ -1,0 +1,275 @@
+"""PyTorch-facing entry points of the HIP path.
+
+Every computation runs in libgs.so; this module only checks tensor
+properties, marshals pointers and the current HIP stream, and wraps the
+forward/backward pairs as ``torch.autograd.Function``s.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, name, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda" or t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 tensor on the GPU")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _ptr_or_null(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Plan:
+    """Workspace and saved forward state of the library (gs_plan)."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        N.call("gs_plan_create", None, None, None, ctypes.byref(h))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def status(self):
+        sk, en = ctypes.c_int64(), ctypes.c_int64()
+        N.call("gs_plan_status", self._h, ctypes.byref(sk), ctypes.byref(en))
+        return {"skipped": sk.value, "tile_entries": en.value}
+
+    def set_timing(self, enable=True):
+        N.call("gs_plan_set_timing", self._h, int(bool(enable)))
+
+    def stage_times(self):
+        """{stage: (total ms, launches)} since the previous query."""
+        n = len(N.STAGES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        N.call("gs_plan_stage_times", self._h, ms, cnt, n)
+        return {N.STAGES[i]: (ms[i], cnt[i]) for i in range(n) if cnt[i]}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            N.lib().gs_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Views:
+    """A host array of gs_view (all views share the detector size)."""
+
+    def __init__(self, arr):
+        self.arr = arr
+        self.n = len(arr)
+        self.width = arr[0].width
+        self.height = arr[0].height
+
+    @classmethod
+    def cone(cls, thetas, src_obj, src_det, width, height, pitch):
+        thetas = list(np.asarray(thetas, np.float64).reshape(-1))
+        arr = (N.GsView * len(thetas))()
+        for i, th in enumerate(thetas):
+            N.call("gs_view_cone", float(th), float(src_obj), float(src_det), int(width),
+                   int(height), float(pitch), ctypes.byref(arr[i]))
+        return cls(arr)
+
+    @classmethod
+    def parallel(cls, rots, width, height, pitch, off_u=0.0, off_v=0.0):
+        rots = np.asarray(rots, np.float64).reshape(-1, 3, 3)
+        arr = (N.GsView * len(rots))()
+        for i, R in enumerate(rots):
+            v = arr[i]
+            v.beam = N.GS_PARALLEL
+            v.width, v.height = int(width), int(height)
+            v.pitch_u = v.pitch_v = float(pitch)
+            v.off_u, v.off_v = float(off_u), float(off_v)
+            for k, x in enumerate(R.reshape(-1)):
+                v.rot[k] = float(x)
+        return cls(arr)
+
+    @classmethod
+    def from_scan(cls, scan):
+        if hasattr(scan, "thetas"):
+            return cls.cone(scan.thetas, scan.src_obj, scan.src_det, scan.width, scan.height,
+                            scan.pitch)
+        return cls.parallel(scan.rots, scan.width, scan.height, scan.pitch)
+
+    def subset(self, idx):
+        idx = list(idx)
+        arr = (N.GsView * len(idx))()
+        for j, i in enumerate(idx):
+            ctypes.memmove(ctypes.byref(arr[j]), ctypes.byref(self.arr[i]), ctypes.sizeof(N.GsView))
+        return Views(arr)
+
+
+def make_grid(nx, ny, nz, origin, spacing):
+    g = N.GsGrid()
+    g.nx, g.ny, g.nz = int(nx), int(ny), int(nz)
+    for k in range(3):
+        g.origin[k] = float(origin[k])
+        g.spacing[k] = float(spacing[k])
+    return g
+
+
+def grid_from(grid):
+    return make_grid(grid.nx, grid.ny, grid.nz, grid.origin, grid.spacing)
+
+
+def _gaussians(mean, scale, quat, density):
+    n = density.shape[0] if density.dim() == 1 else -1
+    g = N.GsGaussians()
+    g.n = n
+    g.mean = _dev(mean, "mean", (n, 3))
+    g.scale = _dev(scale, "scale", (n, 3))
+    g.quat = _dev(quat, "quat", (n, 4))
+    g.density = _dev(density, "density", (n,))
+    return g
+
+
+def _grads(gm, gs, gq, gd):
+    r = N.GsGrads()
+    r.mean, r.scale, r.quat, r.density = (_ptr_or_null(t) for t in (gm, gs, gq, gd))
+    return r
+
+
+# ------------------------------------------------------------------ calls --
+
+def project_forward(mean, scale, quat, density, views: Views, cutoff=3.0, plan=None, out=None):
+    g = _gaussians(mean, scale, quat, density)
+    if out is None:
+        out = torch.empty((views.n, views.height, views.width), device=mean.device,
+                          dtype=torch.float32)
+    N.call("gs_project_fwd", ctypes.byref(g), views.arr, views.n, float(cutoff),
+           _dev(out, "image", (views.n, views.height, views.width)),
+           plan.handle if plan is not None else None, _stream())
+    return out
+
+
+def project_backward(mean, scale, quat, density, views: Views, grad_image, plan, cutoff=3.0,
+                     grads=None, accumulate=False):
+    g = _gaussians(mean, scale, quat, density)
+    if grads is None:
+        grads = tuple(torch.empty_like(t) for t in (mean, scale, quat, density))
+    for t, name in zip(grads, ("mean", "scale", "quat", "density")):
+        if t is not None:
+            _dev(t, "grad_" + name)
+    gr = _grads(*grads)
+    N.call("gs_project_bwd", ctypes.byref(g), views.arr, views.n, float(cutoff),
+           _dev(grad_image, "grad_image", (views.n, views.height, views.width)), ctypes.byref(gr),
+           int(bool(accumulate)), plan.handle, _stream())
+    return grads
+
+
+def voxelize_forward(mean, scale, quat, density, grid, cutoff=3.0, plan=None, out=None):
+    g = _gaussians(mean, scale, quat, density)
+    if out is None:
+        out = torch.empty((grid.nz, grid.ny, grid.nx), device=mean.device, dtype=torch.float32)
+    N.call("gs_voxelize_fwd", ctypes.byref(g), ctypes.byref(grid), float(cutoff),
+           _dev(out, "volume", (grid.nz, grid.ny, grid.nx)),
+           plan.handle if plan is not None else None, _stream())
+    return out
+
+
+def voxelize_backward(mean, scale, quat, density, grid, grad_volume, plan, cutoff=3.0, grads=None,
+                      accumulate=False):
+    g = _gaussians(mean, scale, quat, density)
+    if grads is None:
+        grads = tuple(torch.empty_like(t) for t in (mean, scale, quat, density))
+    gr = _grads(*grads)
+    N.call("gs_voxelize_bwd", ctypes.byref(g), ctypes.byref(grid), float(cutoff),
+           _dev(grad_volume, "grad_volume", (grid.nz, grid.ny, grid.nx)), ctypes.byref(gr),
+           int(bool(accumulate)), plan.handle, _stream())
+    return grads
+
+
+def image_loss(render, measured, plan, lambda_ssim=0.25, grad=True, loss_out=None, grad_out=None):
+    """Returns (loss tensor [3] = total, l1, ssim; grad of total w.r.t. render or None)."""
+    n, h, w = render.shape
+    if loss_out is None:
+        loss_out = torch.empty(3, device=render.device, dtype=torch.float32)
+    if grad and grad_out is None:
+        grad_out = torch.empty_like(render)
+    N.call("gs_loss_image", _dev(render, "render"), _dev(measured, "measured", (n, h, w)), n, h, w,
+           float(lambda_ssim), _dev(loss_out, "loss_out", (3,)),
+           _dev(grad_out, "grad", (n, h, w)) if grad else None, plan.handle, _stream())
+    return loss_out, (grad_out if grad else None)
+
+
+def tv_loss(volume, plan, weight=1.0, grad=True, accumulate=False, loss_out=None, grad_out=None):
+    nz, ny, nx = volume.shape
+    if loss_out is None:
+        loss_out = torch.empty(1, device=volume.device, dtype=torch.float32)
+    if grad and grad_out is None:
+        grad_out = torch.empty_like(volume)
+    N.call("gs_loss_tv", _dev(volume, "volume"), nx, ny, nz, float(weight),
+           _dev(loss_out, "loss_out", (1,)), _dev(grad_out, "grad", (nz, ny, nx)) if grad else None,
+           int(bool(accumulate)), plan.handle, _stream())
+    return loss_out, (grad_out if grad else None)
+
+
+# -------------------------------------------------------------- autograd --
+
+class _Project(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, mean, scale, quat, density, views, cutoff, plan):
+        img = project_forward(mean, scale, quat, density, views, cutoff, plan)
+        ctx.save_for_backward(mean, scale, quat, density)
+        ctx.views, ctx.cutoff, ctx.plan = views, cutoff, plan
+        return img
+
+    @staticmethod
+    def backward(ctx, grad_image):
+        mean, scale, quat, density = ctx.saved_tensors
+        need = ctx.needs_input_grad[:4]
+        grads = tuple(torch.empty_like(t) if nd else None
+                      for t, nd in zip((mean, scale, quat, density), need))
+        project_backward(mean, scale, quat, density, ctx.views, grad_image.contiguous(), ctx.plan,
+                         ctx.cutoff, grads)
+        return (*grads, None, None, None)
+
+
+class _Voxelize(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, mean, scale, quat, density, grid, cutoff, plan):
+        vol = voxelize_forward(mean, scale, quat, density, grid, cutoff, plan)
+        ctx.save_for_backward(mean, scale, quat, density)
+        ctx.grid, ctx.cutoff, ctx.plan = grid, cutoff, plan
+        return vol
+
+    @staticmethod
+    def backward(ctx, grad_volume):
+        mean, scale, quat, density = ctx.saved_tensors
+        need = ctx.needs_input_grad[:4]
+        grads = tuple(torch.empty_like(t) if nd else None
+                      for t, nd in zip((mean, scale, quat, density), need))
+        voxelize_backward(mean, scale, quat, density, ctx.grid, grad_volume.contiguous(), ctx.plan,
+                          ctx.cutoff, grads)
+        return (*grads, None, None, None)
+
+
+def project(mean, scale, quat, density, views: Views, cutoff=3.0, plan=None):
+    """Differentiable X-ray projection [V, H, W] (HIP forward and backward)."""
+    return _Project.apply(mean, scale, quat, density, views, cutoff, plan or Plan())
+
+
+def voxelize(mean, scale, quat, density, grid, cutoff=3.0, plan=None):
+    """Differentiable voxelization [nz, ny, nx] (HIP forward and backward)."""
+    return _Voxelize.apply(mean, scale, quat, density, grid, cutoff, plan or Plan())

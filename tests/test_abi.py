@@ -1,0 +1,105 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/gs.h declares, and host-only helpers behave."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            names += re.findall(r"GS_API\s+[\w\s\*]+?\b(gs_\w+)\s*\(", txt)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def native():
+    from paper_2405_20693_amd import _native
+    if not os.path.exists(_native.LIB_PATH):
+        from paper_2405_20693_amd import build
+        build.build()
+    return _native
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("gs_project_fwd", "gs_project_bwd", "gs_voxelize_fwd", "gs_voxelize_bwd",
+              "gs_plan_create", "gs_plan_destroy", "gs_view_cone", "gs_loss_image", "gs_loss_tv"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(native):
+    lib = native.lib()
+    raw = ctypes.CDLL(native.LIB_PATH)
+    for n in _declared():
+        assert hasattr(raw, n), n
+        assert n in native.EXPORTS, n
+    assert set(native.EXPORTS) == set(_declared())
+    assert lib.gs_last_error() == b""
+
+
+def test_view_cone_matches_scanner_rotation(native):
+    """Host helper: App. A rotation, computed in double and rounded to float,
+    equals the oracle's (independently written) rounding of the same matrix."""
+    v = native.GsView()
+    for th in (0.0, 0.37, 2.1, 5.9):
+        native.call("gs_view_cone", th, 13.64, 20.46, 64, 32, 0.05, ctypes.byref(v))
+        ov = oracle.cone_view(th, 13.64, 20.46, 64, 32, 0.05)
+        np.testing.assert_array_equal(np.array(v.rot[:], np.float64).reshape(3, 3), ov["W"])
+        assert v.beam == native.GS_CONE and v.width == 64 and v.height == 32
+        assert v.src_obj == np.float32(13.64) and v.src_det == np.float32(20.46)
+
+
+def test_view_cone_rejects_bad_geometry(native):
+    v = native.GsView()
+    with pytest.raises(native.GsError, match="GS_EINVAL"):
+        native.call("gs_view_cone", 0.0, 20.0, 10.0, 64, 64, 0.05, ctypes.byref(v))
+    with pytest.raises(native.GsError, match="GS_EINVAL"):
+        native.call("gs_view_cone", 0.0, 10.0, 20.0, 0, 64, 0.05, ctypes.byref(v))
+    with pytest.raises(native.GsError, match="GS_EINVAL"):
+        native.call("gs_view_cone", math.nan, 10.0, 20.0, 8, 8, 0.05, ctypes.byref(v))
+    assert b"theta" in native.lib().gs_last_error()
+
+
+def test_argument_errors_are_caught_before_any_launch(native):
+    """Null pointers and bad sizes return GS_EINVAL from host checks only."""
+    lib = native.lib()
+    g = native.GsGaussians()
+    g.n = 5  # non-zero count with NULL arrays
+    v = native.GsView()
+    native.call("gs_view_cone", 0.0, 10.0, 20.0, 8, 8, 0.05, ctypes.byref(v))
+    st = lib.gs_project_fwd(ctypes.byref(g), ctypes.byref(v), 1, 3.0, None, None, None)
+    assert st == 1 and b"NULL" in lib.gs_last_error()
+    grid = native.GsGrid()
+    grid.nx = 0
+    g.n = 0
+    st = lib.gs_voxelize_fwd(ctypes.byref(g), ctypes.byref(grid), 3.0, ctypes.c_void_p(8), None, None)
+    assert st == 1
+    st = lib.gs_loss_tv(None, 4, 4, 4, 1.0, None, None, 0, None, None)
+    assert st == 1
+    st = lib.gs_plan_create(ctypes.c_void_p(1), None, None, ctypes.byref(ctypes.c_void_p()))
+    assert st == 1  # alloc without free
+
+
+def test_product_path_does_not_use_the_oracle():
+    """The HIP package imports nothing from oracle/ (and vice versa)."""
+    pkg = os.path.join(ROOT, "paper_2405_20693_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
+    for f in os.listdir(os.path.join(ROOT, "oracle")):
+        if f.endswith((".py", ".c")):
+            txt = open(os.path.join(ROOT, "oracle", f)).read()
+            assert "paper_2405_20693_amd" not in txt.replace("``paper_2405_20693_amd``", ""), f

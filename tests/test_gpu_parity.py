@@ -1,0 +1,357 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (oracle/parity.py): forward |gpu - oracle| <= 1e-4 S + amb +
+1e-7 max S per element; gradients <= 1e-3 S_abs + amb per parameter and
+1e-3 in norm per block.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import parity
+from tests import scenes
+import workloads
+from workloads import Grid, upstream
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("mean", "scale", "quat", "density")
+
+
+@pytest.fixture(scope="module")
+def ops():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2405_20693_amd import ops as _ops
+    return _ops
+
+
+def _dev(g):
+    return [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (g.mean, g.scale, g.quat, g.density)]
+
+
+def _np(grads):
+    return {k: t.cpu().numpy() for k, t in zip(KEYS, grads)}
+
+
+def _proj_fwd(ops, g, views, cutoff=3.0):
+    plan = ops.Plan()
+    img = ops.project_forward(*_dev(g), views, cutoff, plan)
+    torch.cuda.synchronize()
+    return img.cpu().numpy(), plan
+
+
+def _report(name, v):
+    print(f"{name}: worst tolerance ratio {v:.3g}", flush=True)
+
+
+# ---------------------------------------------------------------- forward --
+
+def test_c1_parallel_forward(ops):
+    wl = workloads.c1_forward()
+    views = ops.Views.from_scan(wl.scan)
+    img, plan = _proj_fwd(ops, wl.gaussians, views)
+    ref = oracle.project(wl.gaussians, oracle.views_from_scan(wl.scan))
+    v, _ = parity.forward_violation(img, ref)
+    _report("c1 projection", v)
+    assert v <= 1.0
+    st = plan.status()
+    assert st["skipped"] == 0 and st["tile_entries"] > 0
+
+
+def test_c1_voxel_forward(ops):
+    wl = workloads.c1_forward()
+    vol = ops.voxelize_forward(*_dev(wl.gaussians), ops.grid_from(wl.grid), 3.0, ops.Plan())
+    torch.cuda.synchronize()
+    ref = oracle.voxelize(wl.gaussians, wl.grid)
+    v, _ = parity.forward_violation(vol.cpu().numpy(), ref)
+    _report("c1 voxelize", v)
+    assert v <= 1.0
+
+
+@pytest.mark.parametrize("det", [(100, 75), (256, 256), (33, 17)])
+def test_cone_forward_ragged(ops, det):
+    """Cone beam on detectors that are not multiples of the 16-pixel tile,
+    several views and a Gaussian count spanning several binning chunks."""
+    w, h = det
+    wl = workloads.c2_cone(m=9000, n_views=5, det=max(w, h), pitch_mm=1.5 * 256 / max(w, h))
+    thetas = wl.scan.thetas
+    views = ops.Views.cone(thetas, wl.scan.src_obj, wl.scan.src_det, w, h, wl.scan.pitch)
+    oviews = [oracle.cone_view(t, wl.scan.src_obj, wl.scan.src_det, w, h, wl.scan.pitch) for t in thetas]
+    img, _ = _proj_fwd(ops, wl.gaussians, views)
+    ref = oracle.project(wl.gaussians, oviews)
+    v, _ = parity.forward_violation(img, ref)
+    _report(f"cone {det}", v)
+    assert v <= 1.0
+
+
+def test_parallel_offsets_and_rotations(ops):
+    g = scenes.random_scene(31, 400, lo=0.02, hi=0.1, box=0.8)
+    from scipy.spatial.transform import Rotation
+    rots = Rotation.random(3, random_state=5).as_matrix()
+    views = ops.Views.parallel(rots, 90, 70, 0.025, off_u=0.037, off_v=-0.051)
+    ov = [oracle.parallel_view(r, 90, 70, 0.025, 0.037, -0.051) for r in rots]
+    img, _ = _proj_fwd(ops, g, views)
+    v, _ = parity.forward_violation(img, oracle.project(g, ov))
+    _report("parallel offsets", v)
+    assert v <= 1.0
+
+
+def test_no_cutoff_matches_brute_force(ops):
+    g = scenes.random_scene(32, 60, lo=0.03, hi=0.15)
+    views = ops.Views.cone([0.2, 2.9], 13.64, 20.46, 40, 36, 0.05)
+    ov = [oracle.cone_view(t, 13.64, 20.46, 40, 36, 0.05) for t in (0.2, 2.9)]
+    img, _ = _proj_fwd(ops, g, views, cutoff=math.inf)
+    v, _ = parity.forward_violation(img, oracle.project(g, ov, cutoff=math.inf, brute=True))
+    _report("no cutoff", v)
+    assert v <= 1.0
+
+
+def test_voxel_ragged_grid_and_groups(ops):
+    """A grid whose tile planes force several z groups, with ragged edges."""
+    g = scenes.random_scene(33, 3000, lo=0.01, hi=0.05, box=0.9)
+    grid = Grid(300, 230, 45, (-1.0, -0.95, -0.3), (2.0 / 300, 1.9 / 230, 0.6 / 45))
+    vol = ops.voxelize_forward(*_dev(g), ops.grid_from(grid), 3.0, ops.Plan())
+    torch.cuda.synchronize()
+    v, _ = parity.forward_violation(vol.cpu().numpy(), oracle.voxelize(g, grid))
+    _report("voxel ragged", v)
+    assert v <= 1.0
+
+
+# -------------------------------------------------------------- gradients --
+
+def _check_proj_grad(ops, g, views, oviews, seed, cutoff=3.0):
+    G = upstream(seed, (views.n, views.height, views.width))
+    t = _dev(g)
+    plan = ops.Plan()
+    ops.project_forward(*t, views, cutoff, plan)
+    grads = ops.project_backward(*t, views, torch.from_numpy(G).cuda(), plan, cutoff)
+    torch.cuda.synchronize()
+    ref = oracle.project_grad(g, oviews, G, cutoff, with_scale=True)
+    el, nr, det = parity.grad_violation(_np(grads), ref)
+    print("grad detail", det, flush=True)
+    return el, nr
+
+
+@pytest.mark.parametrize("cutoff", [3.0, math.inf])
+def test_cone_gradients(ops, cutoff):
+    g = scenes.random_scene(41, 250, lo=0.03, hi=0.12, box=0.5)
+    th = [0.4, 1.7, 3.3, 5.0]
+    views = ops.Views.cone(th, 13.64, 20.46, 64, 52, 0.045)
+    ov = [oracle.cone_view(t, 13.64, 20.46, 64, 52, 0.045) for t in th]
+    el, nr = _check_proj_grad(ops, g, views, ov, 3, cutoff)
+    _report(f"cone grads cutoff={cutoff}", max(el, nr))
+    assert el <= 1.0 and nr <= 1.0
+
+
+def test_parallel_gradients(ops):
+    from scipy.spatial.transform import Rotation
+    g = scenes.random_scene(42, 200, lo=0.03, hi=0.12, box=0.6)
+    rots = Rotation.random(2, random_state=9).as_matrix()
+    views = ops.Views.parallel(rots, 50, 47, 0.03)
+    ov = [oracle.parallel_view(r, 50, 47, 0.03) for r in rots]
+    el, nr = _check_proj_grad(ops, g, views, ov, 4)
+    _report("parallel grads", max(el, nr))
+    assert el <= 1.0 and nr <= 1.0
+
+
+def test_voxel_gradients(ops):
+    g = scenes.random_scene(43, 200, lo=0.03, hi=0.1, box=0.45)
+    grid = Grid(37, 29, 33, (-0.5, -0.48, -0.52), (1 / 36, 1 / 28, 1 / 32))
+    H = upstream(5, (grid.nz, grid.ny, grid.nx))
+    t = _dev(g)
+    plan = ops.Plan()
+    ops.voxelize_forward(*t, ops.grid_from(grid), 3.0, plan)
+    grads = ops.voxelize_backward(*t, ops.grid_from(grid), torch.from_numpy(H).cuda(), plan, 3.0)
+    torch.cuda.synchronize()
+    ref = oracle.voxelize_grad(g, grid, H, 3.0, with_scale=True)
+    el, nr, det = parity.grad_violation(_np(grads), ref)
+    print(det)
+    _report("voxel grads", max(el, nr))
+    assert el <= 1.0 and nr <= 1.0
+
+
+def test_backward_without_forward_and_accumulate(ops):
+    """Backward on a fresh plan recomputes the binning; accumulate adds."""
+    g = scenes.random_scene(44, 150)
+    views = ops.Views.cone([0.9], 13.64, 20.46, 40, 40, 0.05)
+    G = torch.from_numpy(upstream(6, (1, 40, 40))).cuda()
+    t = _dev(g)
+    a = ops.project_backward(*t, views, G, ops.Plan(), 3.0)
+    plan = ops.Plan()
+    ops.project_forward(*t, views, 3.0, plan)
+    b = ops.project_backward(*t, views, G, plan, 3.0)
+    c = tuple(x.clone() for x in b)
+    ops.project_backward(*t, views, G, plan, 3.0, grads=c, accumulate=True)
+    torch.cuda.synchronize()
+    for x, y, z in zip(a, b, c):
+        assert torch.equal(x, y)
+        assert torch.allclose(z, 2 * y, rtol=1e-6, atol=0)
+
+
+# ----------------------------------------------------------------- losses --
+
+def test_image_loss(ops):
+    x = workloads.random_images(11, 3, 70, 45)
+    y = workloads.random_images(12, 3, 70, 45)
+    loss, grad = ops.image_loss(torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda(), ops.Plan(), 0.25)
+    torch.cuda.synchronize()
+    total, l1, s, gref = oracle.image_loss(x, y, 0.25)
+    lv = loss.cpu().numpy()
+    assert abs(lv[1] - l1) <= 1e-5 * l1 + 1e-7
+    assert abs(lv[2] - s) <= 2e-5
+    assert abs(lv[0] - total) <= 1e-5 * abs(total) + 1e-6
+    gg = grad.cpu().numpy()
+    scale = np.abs(gref).max()
+    assert np.abs(gg - gref).max() <= 1e-3 * scale
+
+
+def test_tv_loss(ops):
+    rng = np.random.default_rng(3)
+    v = rng.standard_normal((13, 17, 19)).astype(np.float32)
+    vt = torch.from_numpy(v).cuda()
+    loss, grad = ops.tv_loss(vt, ops.Plan(), weight=0.05)
+    torch.cuda.synchronize()
+    t, gref = oracle.tv_loss(v, 0.05)
+    assert abs(float(loss.cpu()[0]) - t) <= 1e-5 * t
+    np.testing.assert_allclose(grad.cpu().numpy(), gref, rtol=1e-5, atol=1e-9)
+
+
+# ------------------------------------------------------------ edge cases --
+
+def test_empty_and_degenerate_inputs(ops):
+    views = ops.Views.cone([0.5], 13.64, 20.46, 20, 20, 0.1)
+    z = [torch.zeros((0, k), device="cuda") for k in (3, 3, 4)] + [torch.zeros(0, device="cuda")]
+    img = ops.project_forward(*z, views, 3.0, ops.Plan())
+    assert torch.count_nonzero(img) == 0
+    # NaN centre, zero scale, zero quaternion, a centre behind the source: all skipped
+    bad = scenes.gaussians([[np.nan, 0, 0], [0, 0, 0], [0.1, 0, 0], [30.0, 0.0, 0.0], [0.05, 0.02, 0.0]],
+                           [[0.1] * 3, [0.0, 0.1, 0.1], [0.1] * 3, [0.1] * 3, [0.1] * 3],
+                           [[1, 0, 0, 0], [1, 0, 0, 0], [0, 0, 0, 0], [1, 0, 0, 0], [1, 0, 0, 0]],
+                           [1, 1, 1, 1, 1])
+    ov = [oracle.cone_view(0.0, 13.64, 20.46, 20, 20, 0.1)]
+    views0 = ops.Views.cone([0.0], 13.64, 20.46, 20, 20, 0.1)
+    img, plan = _proj_fwd(ops, bad, views0)
+    assert np.all(np.isfinite(img))
+    v, _ = parity.forward_violation(img, oracle.project(bad, ov))
+    assert v <= 1.0
+    assert plan.status()["skipped"] == 4
+    G = torch.ones((1, 20, 20), device="cuda")
+    grads = ops.project_backward(*_dev(bad), views0, G, plan, 3.0)
+    torch.cuda.synchronize()
+    for t in grads:
+        t = t.cpu().numpy()
+        assert np.all(np.isfinite(t))
+        assert np.all(t[:4] == 0)
+
+
+def test_tiny_detector_and_grid(ops):
+    g = scenes.random_scene(51, 30, lo=0.1, hi=0.3, box=0.2)
+    views = ops.Views.cone([1.0], 13.64, 20.46, 1, 1, 0.3)
+    img, _ = _proj_fwd(ops, g, views)
+    ref = oracle.project(g, [oracle.cone_view(1.0, 13.64, 20.46, 1, 1, 0.3)])
+    assert parity.forward_violation(img, ref)[0] <= 1.0
+    grid = Grid(1, 1, 1, (-0.05, -0.05, -0.05), (0.1, 0.1, 0.1))
+    vol = ops.voxelize_forward(*_dev(g), ops.grid_from(grid), 3.0, ops.Plan())
+    torch.cuda.synchronize()
+    assert parity.forward_violation(vol.cpu().numpy(), oracle.voxelize(g, grid))[0] <= 1.0
+
+
+def test_invalid_arguments_raise(ops):
+    from paper_2405_20693_amd._native import GsError
+    g = scenes.random_scene(52, 10)
+    t = _dev(g)
+    views = ops.Views.cone([0.0], 13.64, 20.46, 16, 16, 0.1)
+    with pytest.raises(GsError, match="GS_EINVAL"):
+        ops.project_forward(*t, views, 0.0, ops.Plan())
+    bad = ops.Views.cone([0.0], 13.64, 20.46, 16, 16, 0.1)
+    bad.arr[0].src_det = 5.0
+    with pytest.raises(GsError, match="GS_EINVAL"):
+        ops.project_forward(*t, bad, 3.0, ops.Plan())
+
+
+# -------------------------------------------------------------- autograd --
+
+def test_autograd_functions_match_direct_calls(ops):
+    g = scenes.random_scene(61, 120)
+    views = ops.Views.cone([0.3, 2.0], 13.64, 20.46, 32, 32, 0.06)
+    t = [x.clone().requires_grad_(True) for x in _dev(g)]
+    img = ops.project(*t, views, 3.0)
+    G = torch.from_numpy(upstream(7, tuple(img.shape))).cuda()
+    (img * G).sum().backward()
+    plan = ops.Plan()
+    d = _dev(g)
+    ops.project_forward(*d, views, 3.0, plan)
+    ref = ops.project_backward(*d, views, G, plan, 3.0)
+    for a, b in zip(t, ref):
+        assert torch.equal(a.grad, b)
+
+
+# ----------------------------------------------------- full-size configs --
+
+def test_c2_full_size_sampled(ops):
+    """C2 (50k Gaussians, 75 cone views of 256^2) in one launch; forward
+    checked on three views, gradients on 48 sampled Gaussians with the upstream
+    gradient supported on those three views."""
+    wl = workloads.c2_cone()
+    views = ops.Views.from_scan(wl.scan)
+    t = _dev(wl.gaussians)
+    plan = ops.Plan()
+    img = ops.project_forward(*t, views, 3.0, plan)
+    sel_v = [0, 31, 62]
+    G = np.zeros((75, 256, 256), np.float32)
+    G[sel_v] = upstream(1, (3, 256, 256))
+    grads = ops.project_backward(*t, views, torch.from_numpy(G).cuda(), plan, 3.0)
+    torch.cuda.synchronize()
+    ov = oracle.views_from_scan(wl.scan)
+    sub = [ov[i] for i in sel_v]
+    ref = oracle.project(wl.gaussians, sub)
+    v, _ = parity.forward_violation(img.cpu().numpy()[sel_v], ref)
+    _report("c2 forward (3 views)", v)
+    assert v <= 1.0
+    sel_g = np.random.default_rng(0).choice(wl.gaussians.n, 48, replace=False)
+    rg = oracle.project_grad(wl.gaussians, sub, G[sel_v], 3.0, select=sel_g, with_scale=True)
+    gg = _np(grads)
+    sub_gpu = {k: gg[k][sel_g] for k in KEYS}
+    sub_ref = {k: rg[k][sel_g] for k in KEYS}
+    sub_ref["S_abs"] = {k: rg["S_abs"][k][sel_g] for k in KEYS}
+    sub_ref["amb"] = {k: rg["amb"][k][sel_g] for k in KEYS}
+    el, nr, det = parity.grad_violation(sub_gpu, sub_ref)
+    print(det)
+    _report("c2 grads (48 Gaussians)", max(el, nr))
+    assert el <= 1.0 and nr <= 1.0
+
+
+def test_training_iteration_matches_oracle_composition(ops):
+    """The fused iteration's gradients equal the oracle's projection gradient
+    of the image-loss gradient plus the voxelization gradient of the weighted
+    TV gradient (small scene)."""
+    from paper_2405_20693_amd.iteration import TrainingIteration
+    g = scenes.random_scene(71, 300, lo=0.03, hi=0.1, box=0.5)
+    th = [0.1, 2.2, 4.1]
+    views = ops.Views.cone(th, 13.64, 20.46, 48, 40, 0.05)
+    ov = [oracle.cone_view(t, 13.64, 20.46, 48, 40, 0.05) for t in th]
+    meas = workloads.random_images(8, 3, 40, 48) * np.float32(0.5)
+    grid = Grid(24, 24, 24, (-0.4, -0.4, -0.4), (1 / 30, 1 / 30, 1 / 30))
+    it = TrainingIteration(*_dev(g), views, torch.from_numpy(meas).cuda(), (24, 24, 24))
+    grads = it.step(ops.grid_from(grid))
+    torch.cuda.synchronize()
+    img = oracle.project(g, ov)["image"]
+    total, l1, s, Gimg = oracle.image_loss(img.astype(np.float32), meas, 0.25)
+    vol = oracle.voxelize(g, grid)["volume"]
+    tv, Hvol = oracle.tv_loss(vol.astype(np.float32), 0.05)
+    lv = it.loss_img.cpu().numpy()
+    assert abs(lv[0] - total) <= 1e-4 * total
+    assert abs(float(it.loss_tv.cpu()[0]) - tv) <= 1e-4 * tv
+    rp = oracle.project_grad(g, ov, Gimg, 3.0, with_scale=True)
+    rv = oracle.voxelize_grad(g, grid, Hvol, 3.0, with_scale=True)
+    comb = {k: rp[k] + rv[k] for k in KEYS}
+    comb["S_abs"] = {k: rp["S_abs"][k] + rv["S_abs"][k] for k in KEYS}
+    comb["amb"] = {k: rp["amb"][k] + rv["amb"][k] for k in KEYS}
+    # the image-loss gradient itself carries FP32 error ~1e-3 relative at worst
+    el, nr, det = parity.grad_violation(_np(grads), comb, rel=3e-3)
+    print(det)
+    assert el <= 1.0 and nr <= 1.0
