@@ -19,6 +19,12 @@ gs_status fail(gs_status st, const std::string &msg) {
   return st;
 }
 
+#define GS_TRY(x)                   \
+  do {                              \
+    gs_status _st = (x);            \
+    if (_st != GS_OK) return _st;   \
+  } while (0)
+
 struct Buf {
   void *p = nullptr;
   size_t cap = 0;
@@ -158,17 +164,20 @@ gs_status ensure(gs_plan *pl, Buf &b, size_t bytes, hipStream_t s) {
   return GS_OK;
 }
 
+// Two skipped counters (projection, voxelization); both start at zero.
+gs_status ensure_skipped(gs_plan *pl, hipStream_t s) {
+  if (pl->skipped.p) return GS_OK;
+  GS_TRY(ensure(pl, pl->skipped, 16, s));
+  if (hipMemsetAsync(pl->skipped.p, 0, 16, s) != hipSuccess) return fail(GS_EHIP, "hipMemsetAsync");
+  return GS_OK;
+}
+
 gs_status check_launch(const char *what) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(GS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
   return GS_OK;
 }
 
-#define GS_TRY(x)                   \
-  do {                              \
-    gs_status _st = (x);            \
-    if (_st != GS_OK) return _st;   \
-  } while (0)
 
 template <class T> T *P(Buf &b) { return reinterpret_cast<T *>(b.p); }
 
@@ -321,7 +330,7 @@ gs_status proj_bin(gs_plan *pl, const gs_gaussians *g, const gs_view *views, int
   GS_TRY(ensure(pl, pl->p_chunk_start, 4 * (VC + 1), s));
   GS_TRY(ensure(pl, pl->p_offsets, 4 * VM, s));
   GS_TRY(ensure(pl, pl->p_totals, 16, s));
-  GS_TRY(ensure(pl, pl->skipped, 16, s));
+  GS_TRY(ensure_skipped(pl, s));
   if (hipMemsetAsync(pl->skipped.p, 0, 8, s) != hipSuccess) return fail(GS_EHIP, "hipMemsetAsync");
   StageTimer t_bin(pl, GS_STAGE_PROJ_BIN, s);
   launch_proj_hist(a, P<Rec2>(pl->p_rec), P<uint32_t>(pl->p_hist), P<uint32_t>(pl->p_chunk_cnt),
@@ -387,7 +396,7 @@ gs_status vox_bin(gs_plan *pl, const gs_gaussians *g, const gs_grid *grid, float
   GS_TRY(ensure(pl, pl->v_tile_total, 4 * (size_t)GT, s));
   GS_TRY(ensure(pl, pl->v_tile_start, 4 * (size_t)(GT + 1), s));
   GS_TRY(ensure(pl, pl->v_totals, 16, s));
-  GS_TRY(ensure(pl, pl->skipped, 16, s));
+  GS_TRY(ensure_skipped(pl, s));
   if (hipMemsetAsync(P<unsigned long long>(pl->skipped) + 1, 0, 8, s) != hipSuccess)
     return fail(GS_EHIP, "hipMemsetAsync");
   StageTimer t_bin(pl, GS_STAGE_VOX_BIN, s);
