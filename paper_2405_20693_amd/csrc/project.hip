@@ -200,15 +200,17 @@ void launch_proj_scatter(const ProjArgs &a, const Rec2 *rec, const uint32_t *his
 
 // One workgroup per (view, 16x16 tile); wave w owns the 8x8 sub-tile
 // (w & 1, w >> 1), one pixel per lane.  The tile's records are staged in LDS
-// in batches of 256; each wave keeps, by ballot, only the records whose cutoff
-// ellipse meets its sub-tile, and sums rho_hat exp2(q') over them (a plain sum:
-// Eq. 7 composes 2D Gaussians additively, so the order is free).
+// in batches of 256; the wave keeps by ballot only the records whose cutoff
+// ellipse meets its sub-tile, and reads each kept record with two broadcast
+// 16-byte LDS loads.  The pixel sums rho_hat exp2(q') over the kept records
+// (a plain sum: Eq. 7 composes 2D Gaussians additively, so the order is free).
+// Branch-free: every kept record is evaluated at every lane and the cutoff is
+// applied with a select, two records per iteration.
 __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *__restrict__ rec,
                                                        const uint32_t *__restrict__ list,
                                                        const uint32_t *__restrict__ tile_start,
                                                        float *__restrict__ image) {
-  __shared__ float s_pu[kBlock], s_pv[kBlock], s_c00[kBlock], s_c01[kBlock], s_c11[kBlock];
-  __shared__ float s_rho[kBlock], s_ia[kBlock], s_ic[kBlock];
+  __shared__ float4 s_r0[kBlock], s_r1[kBlock];
   const int item = xcd_remap(blockIdx.x, gridDim.x);
   const int v = item / a.T, t = item - v * a.T;
   const int ty = t / a.TX, tx = t - ty * a.TX;
@@ -220,41 +222,54 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
   const float ry0 = (float)sy0, ry1 = (float)(sy0 + kSub - 1);
   const uint32_t beg = tile_start[item], end = tile_start[item + 1];
   const Rec2 *rv = rec + (int64_t)v * a.M;
-  float acc = 0.f;
+  const float thr = a.thr;
+  float acc0 = 0.f, acc1 = 0.f;
   for (uint32_t base = beg; base < end; base += kBlock) {
     const int n = (int)min((uint32_t)kBlock, end - base);
     __syncthreads();
     if (tid < n) {
       const uint32_t g = list[base + tid];
       const float4 *p = reinterpret_cast<const float4 *>(rv + g);
-      float4 q0 = p[0], q1 = p[1];
-      s_pu[tid] = q0.x; s_pv[tid] = q0.y; s_c00[tid] = q0.z; s_c01[tid] = q0.w;
-      s_c11[tid] = q1.x; s_rho[tid] = q1.y;
-      s_ia[tid] = -0.5f / q0.z;
-      s_ic[tid] = -0.5f / q1.x;
+      s_r0[tid] = p[0];
+      s_r1[tid] = p[1];
     }
     __syncthreads();
     for (int c0 = 0; c0 < n; c0 += 64) {
       const int i = c0 + lane;
       bool hit = false;
       if (i < n) {
-        const float pu = s_pu[i], pv = s_pv[i];
-        float m = rect_min_form(-s_c00[i], -s_c01[i], -s_c11[i], s_ia[i], s_ic[i], rx0 - pu,
-                                rx1 - pu, ry0 - pv, ry1 - pv);
+        const float4 r0 = s_r0[i], r1 = s_r1[i];
+        const float aa = -r0.z, bb = -r0.w, cc = -r1.x;
+        float m = rect_min_form(aa, bb, cc, 0.5f / aa, 0.5f / cc, rx0 - r0.x, rx1 - r0.x,
+                                ry0 - r0.y, ry1 - r0.y);
         hit = m <= a.qmax;
       }
       uint64_t mask = __ballot(hit);
       while (mask) {
-        const int e = c0 + __builtin_ctzll(mask);
+        const int e0 = c0 + __builtin_ctzll(mask);
         mask &= mask - 1;
-        const float dx = fx - s_pu[e], dy = fy - s_pv[e];
-        const float q = dx * (s_c00[e] * dx + s_c01[e] * dy) + s_c11[e] * dy * dy;
-        const float ex = __builtin_amdgcn_exp2f(q);
-        acc += (q >= a.thr) ? s_rho[e] * ex : 0.f;
+        const bool two = mask != 0;
+        const int e1 = two ? c0 + __builtin_ctzll(mask) : e0;
+        if (two) mask &= mask - 1;
+        const float4 a0 = s_r0[e0], a1 = s_r1[e0];
+        const float4 b0 = s_r0[e1], b1 = s_r1[e1];
+        {
+          const float dx = fx - a0.x, dy = fy - a0.y;
+          const float q = dx * (a0.z * dx + a0.w * dy) + a1.x * dy * dy;
+          const float ex = __builtin_amdgcn_exp2f(q) * a1.y;
+          acc0 += (q >= thr) ? ex : 0.f;
+        }
+        {
+          const float dx = fx - b0.x, dy = fy - b0.y;
+          const float q = dx * (b0.z * dx + b0.w * dy) + b1.x * dy * dy;
+          const float ex = __builtin_amdgcn_exp2f(q) * b1.y;
+          acc1 += (two && q >= thr) ? ex : 0.f;
+        }
       }
     }
   }
-  if (px < a.width && py < a.height) image[((int64_t)v * a.height + py) * a.width + px] = acc;
+  if (px < a.width && py < a.height)
+    image[((int64_t)v * a.height + py) * a.width + px] = acc0 + acc1;
 }
 
 void launch_render_fwd(const ProjArgs &a, const Rec2 *rec, const uint32_t *list,
@@ -282,7 +297,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *_
                                                        float *__restrict__ slots) {
   __shared__ float s_pu[kBlock], s_pv[kBlock], s_c00[kBlock], s_c01[kBlock], s_c11[kBlock];
   __shared__ float s_ia[kBlock], s_ic[kBlock];
-  __shared__ float s_G[kTile * kTile];
+  __shared__ __align__(16) float s_G[kTile * kTile];
   __shared__ float s_acc[4][6][kBlock];
   __shared__ uint16_t s_q[4][kBlock];
   const int item = xcd_remap(blockIdx.x, gridDim.x);
@@ -350,6 +365,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *_
       const float dd = 2.f * c00;
       float S0 = 0.f, S1 = 0.f, S2 = 0.f, S3 = 0.f, S4 = 0.f, S5 = 0.f;
       const float dx0 = rx0 - pu;
+      const float thr = a.thr;
 #pragma unroll 2
       for (int r = 0; r < kSub; ++r) {
         const float dy = ry0 + (float)r - pv;
@@ -357,11 +373,13 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *_
         float q = dx * (c00 * dx + c01 * dy) + c11 * dy * dy;
         float d = c00 * (2.f * dx + 1.f) + c01 * dy;
         float R0 = 0.f, R1 = 0.f, R3 = 0.f;
-        const float *Grow = s_G + (syl + r) * kTile + sxl;
+        const float4 *Grow = reinterpret_cast<const float4 *>(s_G + (syl + r) * kTile + sxl);
+        const float4 ga = Grow[0], gb = Grow[1];
+        const float Gr[kSub] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
 #pragma unroll
         for (int col = 0; col < kSub; ++col) {
-          const float ex = __builtin_amdgcn_exp2f(q);
-          const float ge = (q >= a.thr) ? Grow[col] * ex : 0.f;
+          const float ex = __builtin_amdgcn_exp2f(q) * Gr[col];
+          const float ge = (q >= thr) ? ex : 0.f;
           R0 += ge;
           const float tt = ge * dx;
           R1 += tt;
