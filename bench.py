@@ -40,7 +40,7 @@ def cpu_baseline(wl, measured, target_s=15.0):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     threads = max(1, min(threads, os.cpu_count() or 1))
     nv = len(wl.scan.thetas)
-    k = max(1, min(nv, threads))
+    k = nv if threads >= 8 else max(1, min(nv, 4 * threads))
     views = oracle.views_from_scan(wl.scan)[:k]
     t0 = time.perf_counter()
     img = oracle.project(wl.gaussians, views, wl.cutoff)["image"]
@@ -66,6 +66,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 1 GiB device-to-device (a reference kernel of known "
+                         "traffic for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -82,6 +85,13 @@ def main():
     lib()  # fails loudly if the HIP library is not built
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, device=dev)          # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 1 GiB read + 1 GiB written")
+        del src, dst
     log("generating workload ...")
     wl = workloads.c3_iteration()
     measured = workloads.measured_projections(wl)

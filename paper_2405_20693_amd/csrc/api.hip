@@ -54,7 +54,7 @@ struct gs_plan {
   bool used = false;
   // projection
   Buf p_views, p_rec, p_hist, p_tile_total, p_tile_start, p_chunk_cnt, p_chunk_start, p_offsets,
-      p_list, p_slots, p_totals;
+      p_list, p_slots, p_totals, p_part, p_scan_tmp;
   // voxelization
   Buf v_rec, v_count, v_offsets, v_scan_tmp, v_hist, v_tile_total, v_tile_start, v_list, v_slots,
       v_totals;
@@ -336,9 +336,13 @@ gs_status proj_bin(gs_plan *pl, const gs_gaussians *g, const gs_view *views, int
   launch_proj_hist(a, P<Rec2>(pl->p_rec), P<uint32_t>(pl->p_hist), P<uint32_t>(pl->p_chunk_cnt),
                    P<unsigned long long>(pl->skipped), s);
   launch_hist_colscan(nv, a.C, a.T, P<uint32_t>(pl->p_hist), P<uint32_t>(pl->p_tile_total), s);
-  launch_scan2(P<uint32_t>(pl->p_tile_total), P<uint32_t>(pl->p_tile_start), (int)VT,
-               P<uint32_t>(pl->p_chunk_cnt), P<uint32_t>(pl->p_chunk_start), (int)VC,
-               P<unsigned long long>(pl->p_totals), s);
+  // block-sum scratch of the two multi-block scans: 2 * ceil(n / 4096) + 1 entries each
+  const int64_t tmp_t = 2 * ((VT + 4095) / 4096) + 1, tmp_c = 2 * ((VC + 4095) / 4096) + 1;
+  GS_TRY(ensure(pl, pl->p_scan_tmp, 4 * (size_t)(tmp_t + tmp_c), s));
+  launch_scan_big(P<uint32_t>(pl->p_tile_total), P<uint32_t>(pl->p_tile_start), VT,
+                  P<uint32_t>(pl->p_scan_tmp), P<unsigned long long>(pl->p_totals), s);
+  launch_scan_big(P<uint32_t>(pl->p_chunk_cnt), P<uint32_t>(pl->p_chunk_start), VC,
+                  P<uint32_t>(pl->p_scan_tmp) + tmp_t, P<unsigned long long>(pl->p_totals) + 1, s);
   t_bin.stop();
   GS_TRY(check_launch("projection binning"));
   if (hipMemcpyAsync(pl->readback, pl->p_totals.p, 16, hipMemcpyDeviceToHost, s) != hipSuccess)
@@ -349,10 +353,10 @@ gs_status proj_bin(gs_plan *pl, const gs_gaussians *g, const gs_view *views, int
     return fail(GS_EHIP, "internal error: tile and Gaussian entry totals differ");
   if (entries >= 0xffffffffull)
     return fail(GS_EOVERFLOW, "more than 2^32-1 tile entries: split the views over several calls");
-  GS_TRY(ensure(pl, pl->p_list, 4 * (size_t)entries, s));
+  GS_TRY(ensure(pl, pl->p_list, 8 * (size_t)entries, s));
   StageTimer t_sc(pl, GS_STAGE_PROJ_SCATTER, s);
   launch_proj_scatter(a, P<Rec2>(pl->p_rec), P<uint32_t>(pl->p_hist), P<uint32_t>(pl->p_tile_start),
-                      P<uint32_t>(pl->p_chunk_start), P<uint32_t>(pl->p_list),
+                      P<uint32_t>(pl->p_chunk_start), P<uint2>(pl->p_list),
                       P<uint32_t>(pl->p_offsets), s);
   t_sc.stop();
   GS_TRY(check_launch("projection scatter"));
@@ -476,7 +480,7 @@ void gs_plan_destroy(gs_plan *p) {
   if (p->used) (void)hipDeviceSynchronize();
   Buf *bufs[] = {&p->p_views, &p->p_rec, &p->p_hist, &p->p_tile_total, &p->p_tile_start,
                  &p->p_chunk_cnt, &p->p_chunk_start, &p->p_offsets, &p->p_list, &p->p_slots,
-                 &p->p_totals, &p->v_rec, &p->v_count, &p->v_offsets, &p->v_scan_tmp, &p->v_hist,
+                 &p->p_totals, &p->p_part, &p->p_scan_tmp, &p->v_rec, &p->v_count, &p->v_offsets, &p->v_scan_tmp, &p->v_hist,
                  &p->v_tile_total, &p->v_tile_start, &p->v_list, &p->v_slots, &p->v_totals,
                  &p->l_coef, &p->l_part, &p->skipped};
   for (Buf *b : bufs) release(p, *b);
@@ -582,7 +586,7 @@ gs_status gs_project_fwd(const gs_gaussians *g, const gs_view *views, int32_t n_
   GS_TRY(proj_bin(plan, g, views, n_views, cutoff, stream));
   {
     StageTimer t(plan, GS_STAGE_RENDER_FWD, stream);
-    launch_render_fwd(plan->pargs, P<Rec2>(plan->p_rec), P<uint32_t>(plan->p_list),
+    launch_render_fwd(plan->pargs, P<Rec2>(plan->p_rec), P<uint2>(plan->p_list),
                       P<uint32_t>(plan->p_tile_start), image, stream);
   }
   GS_TRY(check_launch("render forward"));
@@ -606,17 +610,17 @@ gs_status gs_project_bwd(const gs_gaussians *g, const gs_view *views, int32_t n_
     GS_TRY(proj_bin(plan, g, views, n_views, cutoff, stream));
   const ProjArgs &a = plan->pargs;
   GS_TRY(ensure(plan, plan->p_slots, 24 * (size_t)plan->p_entries, stream));
+  GS_TRY(ensure(plan, plan->p_part, 64 * (size_t)proj_chain_chunks(a.V) * (size_t)a.M, stream));
   {
     StageTimer t(plan, GS_STAGE_RENDER_BWD, stream);
-    launch_render_bwd(a, P<Rec2>(plan->p_rec), P<uint32_t>(plan->p_list),
-                      P<uint32_t>(plan->p_tile_start), P<uint32_t>(plan->p_offsets), grad_image,
-                      P<float>(plan->p_slots), stream);
+    launch_render_bwd(a, P<Rec2>(plan->p_rec), P<uint2>(plan->p_list),
+                      P<uint32_t>(plan->p_tile_start), grad_image, P<float>(plan->p_slots), stream);
   }
   {
     StageTimer t(plan, GS_STAGE_PROJ_CHAIN, stream);
     launch_proj_chain(a, P<Rec2>(plan->p_rec), P<uint32_t>(plan->p_offsets),
-                      P<float>(plan->p_slots), grads->mean, grads->scale, grads->quat,
-                      grads->density, accumulate, stream);
+                      P<float>(plan->p_slots), P<float>(plan->p_part), grads->mean, grads->scale,
+                      grads->quat, grads->density, accumulate, stream);
   }
   return check_launch("projection backward");
 }

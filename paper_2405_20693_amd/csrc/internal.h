@@ -268,17 +268,19 @@ void launch_hist_colscan(int groups, int C, int T, uint32_t *hist, uint32_t *til
                          hipStream_t s);
 void launch_scan2(const uint32_t *in0, uint32_t *out0, int n0, const uint32_t *in1, uint32_t *out1,
                   int n1, unsigned long long *totals, hipStream_t s);
+// Tile-list entries are (Gaussian index, backward slot) pairs.
 void launch_proj_scatter(const ProjArgs &a, const Rec2 *rec, const uint32_t *hist,
-                         const uint32_t *tile_start, const uint32_t *chunk_start, uint32_t *list,
+                         const uint32_t *tile_start, const uint32_t *chunk_start, uint2 *list,
                          uint32_t *offsets, hipStream_t s);
-void launch_render_fwd(const ProjArgs &a, const Rec2 *rec, const uint32_t *list,
+void launch_render_fwd(const ProjArgs &a, const Rec2 *rec, const uint2 *list,
                        const uint32_t *tile_start, float *image, hipStream_t s);
-void launch_render_bwd(const ProjArgs &a, const Rec2 *rec, const uint32_t *list,
-                       const uint32_t *tile_start, const uint32_t *offsets, const float *grad_image,
-                       float *slots, hipStream_t s);
+void launch_render_bwd(const ProjArgs &a, const Rec2 *rec, const uint2 *list,
+                       const uint32_t *tile_start, const float *grad_image, float *slots,
+                       hipStream_t s);
+int proj_chain_chunks(int n_views);  // partial-gradient chunks (16 floats per Gaussian each)
 void launch_proj_chain(const ProjArgs &a, const Rec2 *rec, const uint32_t *offsets,
-                       const float *slots, float *g_mean, float *g_scale, float *g_quat,
-                       float *g_dens, int accumulate, hipStream_t s);
+                       const float *slots, float *part, float *g_mean, float *g_scale,
+                       float *g_quat, float *g_dens, int accumulate, hipStream_t s);
 
 struct VoxArgs {
   const float *mean, *scale, *quat, *dens;

@@ -154,7 +154,7 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
                                                          const uint32_t *__restrict__ hist,
                                                          const uint32_t *__restrict__ tile_start,
                                                          const uint32_t *__restrict__ chunk_start,
-                                                         uint32_t *__restrict__ list,
+                                                         uint2 *__restrict__ list,
                                                          uint32_t *__restrict__ offsets) {
   extern __shared__ uint32_t cur[];
   __shared__ uint32_t sh4[4];
@@ -179,17 +179,18 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
     uint32_t total;
     uint32_t ex = block_excl_scan((uint32_t)n, sh4, total);
     if (valid) offsets[(int64_t)v * a.M + g] = base + ex;
+    uint32_t slot = base + ex;  // slots of this (view, Gaussian): its tiles in row-major order
     for (int ty = rc.y0; ty <= rc.y1 && n; ++ty)
       for (int tx = rc.x0; tx <= rc.x1; ++tx) {
         uint32_t pos = atomicAdd(&cur[ty * a.TX + tx], 1u);
-        list[pos] = (uint32_t)g;
+        list[pos] = make_uint2((uint32_t)g, slot++);
       }
     base += total;
   }
 }
 
 void launch_proj_scatter(const ProjArgs &a, const Rec2 *rec, const uint32_t *hist,
-                         const uint32_t *tile_start, const uint32_t *chunk_start, uint32_t *list,
+                         const uint32_t *tile_start, const uint32_t *chunk_start, uint2 *list,
                          uint32_t *offsets, hipStream_t s) {
   dim3 grid(a.C, a.V);
   hipLaunchKernelGGL(k_proj_scatter, grid, dim3(kBlock), a.T * sizeof(uint32_t), s, a, rec, hist,
@@ -200,26 +201,30 @@ void launch_proj_scatter(const ProjArgs &a, const Rec2 *rec, const uint32_t *his
 
 // One workgroup per (view, 16x16 tile); wave w owns the 8x8 sub-tile
 // (w & 1, w >> 1), one pixel per lane.  The tile's records are staged in LDS
-// in batches of 256; the wave keeps by ballot only the records whose cutoff
-// ellipse meets its sub-tile, and reads each kept record with two broadcast
-// 16-byte LDS loads.  The pixel sums rho_hat exp2(q') over the kept records
-// (a plain sum: Eq. 7 composes 2D Gaussians additively, so the order is free).
-// Branch-free: every kept record is evaluated at every lane and the cutoff is
-// applied with a select, two records per iteration.
+// in batches of 256.  For each chunk of 64 records, lane i tests record i
+// against the wave's sub-tile (exact minimum of the quadratic form over the
+// sub-tile) and, if it hits, rewrites it relative to the sub-tile centre as
+//   q' + log2|rho_hat| = K0 + K1 x + K2 y + c00 x^2 + c01 x y + c11 y^2
+// (x, y: lane offsets from the centre), so that each kept record costs five
+// FMAs, one exp2 and a select per pixel.  The pixel sums sign(rho_hat)
+// exp2(...) over the kept records (a plain sum: Eq. 7 composes 2D Gaussians
+// additively, so the order is free).
 __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *__restrict__ rec,
-                                                       const uint32_t *__restrict__ list,
+                                                       const uint2 *__restrict__ list,
                                                        const uint32_t *__restrict__ tile_start,
                                                        float *__restrict__ image) {
   __shared__ float4 s_r0[kBlock], s_r1[kBlock];
+  __shared__ float4 s_k0[4][64], s_k1[4][64];
   const int item = xcd_remap(blockIdx.x, gridDim.x);
   const int v = item / a.T, t = item - v * a.T;
   const int ty = t / a.TX, tx = t - ty * a.TX;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int sx0 = tx * kTile + (w & 1) * kSub, sy0 = ty * kTile + (w >> 1) * kSub;
   const int px = sx0 + (lane & 7), py = sy0 + (lane >> 3);
-  const float fx = (float)px, fy = (float)py;
-  const float rx0 = (float)sx0, rx1 = (float)(sx0 + kSub - 1);
-  const float ry0 = (float)sy0, ry1 = (float)(sy0 + kSub - 1);
+  const float cxs = (float)sx0 + 0.5f * (kSub - 1), cys = (float)sy0 + 0.5f * (kSub - 1);
+  const float lx = (float)(lane & 7) - 0.5f * (kSub - 1), ly = (float)(lane >> 3) - 0.5f * (kSub - 1);
+  const float lxx = lx * lx, lxy = lx * ly, lyy = ly * ly;
+  const float hs = 0.5f * (kSub - 1);
   const uint32_t beg = tile_start[item], end = tile_start[item + 1];
   const Rec2 *rv = rec + (int64_t)v * a.M;
   const float thr = a.thr;
@@ -228,7 +233,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
     const int n = (int)min((uint32_t)kBlock, end - base);
     __syncthreads();
     if (tid < n) {
-      const uint32_t g = list[base + tid];
+      const uint32_t g = list[base + tid].x;
       const float4 *p = reinterpret_cast<const float4 *>(rv + g);
       s_r0[tid] = p[0];
       s_r1[tid] = p[1];
@@ -239,40 +244,60 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
       bool hit = false;
       if (i < n) {
         const float4 r0 = s_r0[i], r1 = s_r1[i];
-        const float aa = -r0.z, bb = -r0.w, cc = -r1.x;
-        float m = rect_min_form(aa, bb, cc, 0.5f / aa, 0.5f / cc, rx0 - r0.x, rx1 - r0.x,
-                                ry0 - r0.y, ry1 - r0.y);
-        hit = m <= a.qmax;
+        const float c00 = r0.z, c01 = r0.w, c11 = r1.x, rho = r1.y;
+        const float u = r0.x - cxs, vv = r0.y - cys;  // centre relative to the sub-tile centre
+        const float aa = -c00, bb = -c01, cc = -c11;
+        const float m = rect_min_form(aa, bb, cc, 0.5f / aa, 0.5f / cc, -hs - u, hs - u, -hs - vv,
+                                      hs - vv);
+        hit = m <= a.qmax && rho != 0.f;
+        if (hit) {
+          const float lr = __log2f(fabsf(rho));
+          const float K0 = u * (c00 * u + c01 * vv) + c11 * vv * vv + lr;
+          const float K1 = -(2.f * c00 * u + c01 * vv);
+          const float K2 = -(c01 * u + 2.f * c11 * vv);
+          s_k0[w][lane] = make_float4(K0, K1, K2, c00);
+          s_k1[w][lane] = make_float4(c01, c11, thr + lr, rho > 0.f ? 1.f : -1.f);
+        }
       }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       uint64_t mask = __ballot(hit);
       while (mask) {
-        const int e0 = c0 + __builtin_ctzll(mask);
+        const int j0 = __builtin_ctzll(mask);
         mask &= mask - 1;
         const bool two = mask != 0;
-        const int e1 = two ? c0 + __builtin_ctzll(mask) : e0;
+        const int j1 = two ? __builtin_ctzll(mask) : j0;
         if (two) mask &= mask - 1;
-        const float4 a0 = s_r0[e0], a1 = s_r1[e0];
-        const float4 b0 = s_r0[e1], b1 = s_r1[e1];
+        const float4 a0 = s_k0[w][j0], a1 = s_k1[w][j0];
+        const float4 b0 = s_k0[w][j1], b1 = s_k1[w][j1];
         {
-          const float dx = fx - a0.x, dy = fy - a0.y;
-          const float q = dx * (a0.z * dx + a0.w * dy) + a1.x * dy * dy;
-          const float ex = __builtin_amdgcn_exp2f(q) * a1.y;
-          acc0 += (q >= thr) ? ex : 0.f;
+          float q = fmaf(a0.y, lx, a0.x);
+          q = fmaf(a0.z, ly, q);
+          q = fmaf(a0.w, lxx, q);
+          q = fmaf(a1.x, lxy, q);
+          q = fmaf(a1.y, lyy, q);
+          const float e = (q >= a1.z) ? __builtin_amdgcn_exp2f(q) : 0.f;
+          acc0 = fmaf(a1.w, e, acc0);
         }
         {
-          const float dx = fx - b0.x, dy = fy - b0.y;
-          const float q = dx * (b0.z * dx + b0.w * dy) + b1.x * dy * dy;
-          const float ex = __builtin_amdgcn_exp2f(q) * b1.y;
-          acc1 += (two && q >= thr) ? ex : 0.f;
+          float q = fmaf(b0.y, lx, b0.x);
+          q = fmaf(b0.z, ly, q);
+          q = fmaf(b0.w, lxx, q);
+          q = fmaf(b1.x, lxy, q);
+          q = fmaf(b1.y, lyy, q);
+          const float e = (two && q >= b1.z) ? __builtin_amdgcn_exp2f(q) : 0.f;
+          acc1 = fmaf(b1.w, e, acc1);
         }
       }
+      __builtin_amdgcn_wave_barrier();  // the next chunk overwrites this wave's coefficients
     }
   }
   if (px < a.width && py < a.height)
     image[((int64_t)v * a.height + py) * a.width + px] = acc0 + acc1;
 }
 
-void launch_render_fwd(const ProjArgs &a, const Rec2 *rec, const uint32_t *list,
+void launch_render_fwd(const ProjArgs &a, const Rec2 *rec, const uint2 *list,
                        const uint32_t *tile_start, float *image, hipStream_t s) {
   int n = a.V * a.T;
   hipLaunchKernelGGL(k_render_fwd, dim3(n), dim3(kBlock), 0, s, a, rec, list, tile_start, image);
@@ -290,9 +315,8 @@ void launch_render_fwd(const ProjArgs &a, const Rec2 *rec, const uint32_t *list,
 // entries, so no cross-lane reduction is needed; the four waves' moments are
 // summed in a fixed order and written to the entry's slot (deterministic).
 __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *__restrict__ rec,
-                                                       const uint32_t *__restrict__ list,
+                                                       const uint2 *__restrict__ list,
                                                        const uint32_t *__restrict__ tile_start,
-                                                       const uint32_t *__restrict__ offsets,
                                                        const float *__restrict__ grad_image,
                                                        float *__restrict__ slots) {
   __shared__ float s_pu[kBlock], s_pv[kBlock], s_c00[kBlock], s_c01[kBlock], s_c11[kBlock];
@@ -317,21 +341,19 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *_
   }
   const uint32_t beg = tile_start[item], end = tile_start[item + 1];
   const Rec2 *rv = rec + (int64_t)v * a.M;
-  const uint32_t *ov = offsets + (int64_t)v * a.M;
   for (uint32_t base = beg; base < end; base += kBlock) {
     const int n = (int)min((uint32_t)kBlock, end - base);
     __syncthreads();
     uint32_t my_slot = 0;
     if (tid < n) {
-      const uint32_t g = list[base + tid];
-      const float4 *p = reinterpret_cast<const float4 *>(rv + g);
+      const uint2 ent = list[base + tid];
+      my_slot = ent.y;
+      const float4 *p = reinterpret_cast<const float4 *>(rv + ent.x);
       float4 q0 = p[0], q1 = p[1];
       s_pu[tid] = q0.x; s_pv[tid] = q0.y; s_c00[tid] = q0.z; s_c01[tid] = q0.w;
       s_c11[tid] = q1.x;
       s_ia[tid] = -0.5f / q0.z;
       s_ic[tid] = -0.5f / q1.x;
-      Rect2 rc = unpack_rect(__float_as_uint(q1.z), __float_as_uint(q1.w));
-      my_slot = ov[g] + (uint32_t)((ty - rc.y0) * (rc.x1 - rc.x0 + 1) + (tx - rc.x0));
     }
 #pragma unroll
     for (int k = 0; k < 6; ++k)
@@ -410,35 +432,41 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *_
   }
 }
 
-void launch_render_bwd(const ProjArgs &a, const Rec2 *rec, const uint32_t *list,
-                       const uint32_t *tile_start, const uint32_t *offsets, const float *grad_image,
-                       float *slots, hipStream_t s) {
+void launch_render_bwd(const ProjArgs &a, const Rec2 *rec, const uint2 *list,
+                       const uint32_t *tile_start, const float *grad_image, float *slots,
+                       hipStream_t s) {
   int n = a.V * a.T;
-  hipLaunchKernelGGL(k_render_bwd, dim3(n), dim3(kBlock), 0, s, a, rec, list, tile_start, offsets,
+  hipLaunchKernelGGL(k_render_bwd, dim3(n), dim3(kBlock), 0, s, a, rec, list, tile_start,
                      grad_image, slots);
 }
 
 // ------------------------------------------------- per-Gaussian chain rule --
 
-// One thread per Gaussian, looping over views in order (deterministic): sums
-// the moments of its tile slots, converts them to the gradients of rho_hat,
-// the projected centre and the conic, and applies the chain rule through the
+// Per (Gaussian, chunk of views), views in order (deterministic): sums the
+// moments of its tile slots, converts them to the gradients of rho_hat, the
+// projected centre and the conic, and applies the chain rule through the
 // inverse, Sigma_hat = B B^T with B = J W R S, the rectification factor
 // mu = sqrt(2 pi / (d^T Sigma^{-1} d)), the perspective Jacobian J(t), the
-// perspective division and t = W p + t0.
+// perspective division and t = W p + t0.  Writes the chunk's partial
+// gradients with respect to p, s, R and rho (16 values, component-major);
+// k_proj_chain_reduce sums the chunks in order and finishes the quaternion.
+constexpr int kChainViews = 8;
+constexpr int kChainParts = 16;
+
 __global__ __launch_bounds__(kBlock) void k_proj_chain(ProjArgs a, const Rec2 *__restrict__ rec,
                                                        const uint32_t *__restrict__ offsets,
                                                        const float *__restrict__ slots,
-                                                       float *g_mean, float *g_scale, float *g_quat,
-                                                       float *g_dens, int accumulate) {
+                                                       float *__restrict__ part) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (g >= a.M) return;
+  const int vc = blockIdx.y;
   Gauss G;
   load_gauss(a.mean, a.scale, a.quat, a.dens, g, G);
   float gp[3] = {0.f, 0.f, 0.f}, gs[3] = {0.f, 0.f, 0.f}, gR[9] = {0.f};
   float grho = 0.f;
+  const int v0 = vc * kChainViews, v1 = min(v0 + kChainViews, a.V);
   if (G.ok) {
-    for (int v = 0; v < a.V; ++v) {
+    for (int v = v0; v < v1; ++v) {
       const int64_t vg = (int64_t)v * a.M + g;
       const Rec2 r = rec[vg];
       const Rect2 rc = unpack_rect(r.r0, r.r1);
@@ -530,23 +558,49 @@ __global__ __launch_bounds__(kBlock) void k_proj_chain(ProjArgs a, const Rec2 *_
       for (int i = 0; i < 3; ++i) gp[i] += W[i] * gt[0] + W[3 + i] * gt[1] + W[6 + i] * gt[2];
     }
   }
-  float gq[4] = {0.f, 0.f, 0.f, 0.f};
-  if (G.ok) quat_backward(G, gR, gq);
-  if (g_mean)
-    for (int i = 0; i < 3; ++i) g_mean[3 * g + i] = accumulate ? g_mean[3 * g + i] + gp[i] : gp[i];
-  if (g_scale)
-    for (int i = 0; i < 3; ++i)
-      g_scale[3 * g + i] = accumulate ? g_scale[3 * g + i] + gs[i] : gs[i];
-  if (g_quat)
-    for (int i = 0; i < 4; ++i) g_quat[4 * g + i] = accumulate ? g_quat[4 * g + i] + gq[i] : gq[i];
-  if (g_dens) g_dens[g] = accumulate ? g_dens[g] + grho : grho;
+  float *o = part + (int64_t)vc * kChainParts * a.M + g;
+  for (int i = 0; i < 3; ++i) o[(int64_t)i * a.M] = gp[i];
+  for (int i = 0; i < 3; ++i) o[(int64_t)(3 + i) * a.M] = gs[i];
+  for (int i = 0; i < 9; ++i) o[(int64_t)(6 + i) * a.M] = gR[i];
+  o[(int64_t)15 * a.M] = grho;
 }
 
+__global__ __launch_bounds__(kBlock) void k_proj_chain_reduce(ProjArgs a, int n_chunks,
+                                                              const float *__restrict__ part,
+                                                              float *g_mean, float *g_scale,
+                                                              float *g_quat, float *g_dens,
+                                                              int accumulate) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= a.M) return;
+  float sum[kChainParts];
+  for (int k = 0; k < kChainParts; ++k) sum[k] = 0.f;
+  for (int c = 0; c < n_chunks; ++c) {
+    const float *o = part + (int64_t)c * kChainParts * a.M + g;
+    for (int k = 0; k < kChainParts; ++k) sum[k] += o[(int64_t)k * a.M];
+  }
+  Gauss G;
+  load_gauss(a.mean, a.scale, a.quat, a.dens, g, G);
+  float gq[4] = {0.f, 0.f, 0.f, 0.f};
+  if (G.ok) quat_backward(G, sum + 6, gq);
+  if (g_mean)
+    for (int i = 0; i < 3; ++i) g_mean[3 * g + i] = accumulate ? g_mean[3 * g + i] + sum[i] : sum[i];
+  if (g_scale)
+    for (int i = 0; i < 3; ++i)
+      g_scale[3 * g + i] = accumulate ? g_scale[3 * g + i] + sum[3 + i] : sum[3 + i];
+  if (g_quat)
+    for (int i = 0; i < 4; ++i) g_quat[4 * g + i] = accumulate ? g_quat[4 * g + i] + gq[i] : gq[i];
+  if (g_dens) g_dens[g] = accumulate ? g_dens[g] + sum[15] : sum[15];
+}
+
+int proj_chain_chunks(int n_views) { return (n_views + kChainViews - 1) / kChainViews; }
+
 void launch_proj_chain(const ProjArgs &a, const Rec2 *rec, const uint32_t *offsets,
-                       const float *slots, float *g_mean, float *g_scale, float *g_quat,
-                       float *g_dens, int accumulate, hipStream_t s) {
+                       const float *slots, float *part, float *g_mean, float *g_scale,
+                       float *g_quat, float *g_dens, int accumulate, hipStream_t s) {
   unsigned nb = (unsigned)((a.M + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_proj_chain, dim3(nb), dim3(kBlock), 0, s, a, rec, offsets, slots, g_mean,
+  const int nc = proj_chain_chunks(a.V);
+  hipLaunchKernelGGL(k_proj_chain, dim3(nb, nc), dim3(kBlock), 0, s, a, rec, offsets, slots, part);
+  hipLaunchKernelGGL(k_proj_chain_reduce, dim3(nb), dim3(kBlock), 0, s, a, nc, part, g_mean,
                      g_scale, g_quat, g_dens, accumulate);
 }
 

@@ -121,10 +121,15 @@ void launch_scan_big(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *blo
 }
 
 // ------------------------------------------------------------------ SSIM --
-// Tiles of 32 x 16 output pixels per 256-thread workgroup with a 5-pixel halo;
-// the 11-tap normalised Gaussian window (sigma 1.5) is separable.
+// Tiles of 32 x 32 output pixels per 256-thread workgroup with a 5-pixel halo;
+// the 11-tap normalised Gaussian window (sigma 1.5) is separable.  Both passes
+// are register-blocked: a thread computes 4 horizontally adjacent outputs of
+// the row pass from one 14-value window, and 4 vertically adjacent outputs of
+// the column pass from one 14-value window.
 
-constexpr int kSW = 32, kSH = 16, kR = 5, kWin = 2 * kR + 1;
+constexpr int kSW = 32, kSH = 32, kR = 5, kWin = 2 * kR + 1;
+constexpr int kIW = kSW + 2 * kR, kIH = kSH + 2 * kR;  // 42 x 42 input region
+constexpr int kRB = 4;                                  // outputs per thread per pass
 constexpr float kC1 = 0.0001f, kC2 = 0.0009f;
 
 __constant__ float c_win[kWin];
@@ -148,6 +153,48 @@ int ssim_num_blocks(int n, int h, int w) {
   return n * ((h + kSH - 1) / kSH) * ((w + kSW - 1) / kSW);
 }
 
+// Row pass of Q planes: out[q][r][c] = sum_k w_k in[q][r][c + k], for the
+// kIH rows and kSW output columns; 4 columns per task.
+template <int Q>
+__device__ inline void row_pass(const float (*in)[kIH][kIW], float (*out)[kIH][kSW]) {
+  constexpr int tasks = kIH * (kSW / kRB);
+  for (int task = threadIdx.x; task < tasks; task += kBlock) {
+    const int r = task / (kSW / kRB), c0 = (task - r * (kSW / kRB)) * kRB;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      float win[kRB + kWin - 1];
+#pragma unroll
+      for (int k = 0; k < kRB + kWin - 1; ++k) win[k] = in[q][r][c0 + k];
+#pragma unroll
+      for (int o = 0; o < kRB; ++o) {
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < kWin; ++k) acc = fmaf(c_win[k], win[o + k], acc);
+        out[q][r][c0 + o] = acc;
+      }
+    }
+  }
+}
+
+// Column pass: 4 consecutive output rows of one column per thread (256 tasks).
+template <int Q>
+__device__ inline void col_pass(const float (*hz)[kIH][kSW], float (*m)[kRB]) {
+  const int c = threadIdx.x & (kSW - 1), r0 = (threadIdx.x / kSW) * kRB;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    float win[kRB + kWin - 1];
+#pragma unroll
+    for (int k = 0; k < kRB + kWin - 1; ++k) win[k] = hz[q][r0 + k][c];
+#pragma unroll
+    for (int o = 0; o < kRB; ++o) {
+      float acc = 0.f;
+#pragma unroll
+      for (int k = 0; k < kWin; ++k) acc = fmaf(c_win[k], win[o + k], acc);
+      m[q][o] = acc;
+    }
+  }
+}
+
 // Computes the per-pixel SSIM map and the coefficient maps
 //   D1 = dS/dmu_x - 2 mu_x dS/dsxx - mu_y dS/dsxy,  D2 = dS/dsxx,  D3 = dS/dsxy
 // so that d mean(S) / d x = (blur(D1) + 2 x blur(D2) + y blur(D3)) / N.
@@ -156,9 +203,8 @@ __global__ __launch_bounds__(kBlock) void k_ssim_coeffs(const float *__restrict_
                                                         const float *__restrict__ y, int n, int h,
                                                         int w, float *__restrict__ coef,
                                                         float *__restrict__ partials) {
-  constexpr int IW = kSW + 2 * kR, IH = kSH + 2 * kR;
-  __shared__ float sx[IH][IW], sy[IH][IW];
-  __shared__ float hz[5][IH][kSW];
+  __shared__ float sin_[2][kIH][kIW];   // x, y
+  __shared__ float hz[5][kIH][kSW];
   __shared__ float red[2][kBlock];
   const int tiles_x = (w + kSW - 1) / kSW, tiles_y = (h + kSH - 1) / kSH;
   const int b = blockIdx.x;
@@ -167,44 +213,53 @@ __global__ __launch_bounds__(kBlock) void k_ssim_coeffs(const float *__restrict_
   const int X0 = tx * kSW - kR, Y0 = ty * kSH - kR;
   const float *xi = x + (int64_t)img * h * w, *yi = y + (int64_t)img * h * w;
   const int tid = threadIdx.x;
-  for (int i = tid; i < IW * IH; i += kBlock) {
-    const int r = i / IW, c = i - r * IW;
+  for (int i = tid; i < kIW * kIH; i += kBlock) {
+    const int r = i / kIW, c = i - r * kIW;
     const int gy = Y0 + r, gx = X0 + c;
     const bool in = gx >= 0 && gx < w && gy >= 0 && gy < h;
-    sx[r][c] = in ? xi[(int64_t)gy * w + gx] : 0.f;
-    sy[r][c] = in ? yi[(int64_t)gy * w + gx] : 0.f;
+    const float xv = in ? xi[(int64_t)gy * w + gx] : 0.f;
+    const float yv = in ? yi[(int64_t)gy * w + gx] : 0.f;
+    sin_[0][r][c] = xv;
+    sin_[1][r][c] = yv;
   }
   __syncthreads();
-  for (int i = tid; i < IH * kSW; i += kBlock) {
-    const int r = i / kSW, c = i - r * kSW;
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f;
+  // row pass of x, y, x^2, y^2, xy from the x and y windows
+  for (int task = tid; task < kIH * (kSW / kRB); task += kBlock) {
+    const int r = task / (kSW / kRB), c0 = (task - r * (kSW / kRB)) * kRB;
+    float wx[kRB + kWin - 1], wy[kRB + kWin - 1];
 #pragma unroll
-    for (int k = 0; k < kWin; ++k) {
-      const float wk = c_win[k], xv = sx[r][c + k], yv = sy[r][c + k];
-      a0 = fmaf(wk, xv, a0);
-      a1 = fmaf(wk, yv, a1);
-      a2 = fmaf(wk, xv * xv, a2);
-      a3 = fmaf(wk, yv * yv, a3);
-      a4 = fmaf(wk, xv * yv, a4);
+    for (int k = 0; k < kRB + kWin - 1; ++k) {
+      wx[k] = sin_[0][r][c0 + k];
+      wy[k] = sin_[1][r][c0 + k];
     }
-    hz[0][r][c] = a0; hz[1][r][c] = a1; hz[2][r][c] = a2; hz[3][r][c] = a3; hz[4][r][c] = a4;
+#pragma unroll
+    for (int o = 0; o < kRB; ++o) {
+      float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f;
+#pragma unroll
+      for (int k = 0; k < kWin; ++k) {
+        const float wk = c_win[k], xv = wx[o + k], yv = wy[o + k];
+        a0 = fmaf(wk, xv, a0);
+        a1 = fmaf(wk, yv, a1);
+        a2 = fmaf(wk, xv * xv, a2);
+        a3 = fmaf(wk, yv * yv, a3);
+        a4 = fmaf(wk, xv * yv, a4);
+      }
+      hz[0][r][c0 + o] = a0; hz[1][r][c0 + o] = a1; hz[2][r][c0 + o] = a2;
+      hz[3][r][c0 + o] = a3; hz[4][r][c0 + o] = a4;
+    }
   }
   __syncthreads();
-  float ssum = 0.f, lsum = 0.f;
+  float m[5][kRB];
+  col_pass<5>(hz, m);
+  const int c = tid & (kSW - 1), r0 = (tid / kSW) * kRB;
   const int64_t N = (int64_t)n * h * w;
-  for (int i = tid; i < kSH * kSW; i += kBlock) {
-    const int r = i / kSW, c = i - r * kSW;
-    const int gy = ty * kSH + r, gx = tx * kSW + c;
+  float ssum = 0.f, lsum = 0.f;
+#pragma unroll
+  for (int o = 0; o < kRB; ++o) {
+    const int gy = ty * kSH + r0 + o, gx = tx * kSW + c;
     if (gx >= w || gy >= h) continue;
-    float m[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int k = 0; k < kWin; ++k) {
-      const float wk = c_win[k];
-#pragma unroll
-      for (int q = 0; q < 5; ++q) m[q] = fmaf(wk, hz[q][r + k][c], m[q]);
-    }
-    const float mx = m[0], my = m[1];
-    const float sxx = m[2] - mx * mx, syy = m[3] - my * my, sxy = m[4] - mx * my;
+    const float mx = m[0][o], my = m[1][o];
+    const float sxx = m[2][o] - mx * mx, syy = m[3][o] - my * my, sxy = m[4][o] - mx * my;
     const float A1 = 2.f * mx * my + kC1, A2 = 2.f * sxy + kC2;
     const float B1 = mx * mx + my * my + kC1, B2 = sxx + syy + kC2;
     const float iB = 1.f / (B1 * B2);
@@ -212,12 +267,12 @@ __global__ __launch_bounds__(kBlock) void k_ssim_coeffs(const float *__restrict_
     const float dmx = 2.f * my * A2 * iB - 2.f * mx * S / B1;
     const float dsxx = -S / B2;
     const float dsxy = 2.f * A1 * iB;
-    const int64_t o = (int64_t)img * h * w + (int64_t)gy * w + gx;
-    coef[o] = dmx - 2.f * mx * dsxx - my * dsxy;
-    coef[N + o] = dsxx;
-    coef[2 * N + o] = dsxy;
+    const int64_t off = (int64_t)img * h * w + (int64_t)gy * w + gx;
+    coef[off] = dmx - 2.f * mx * dsxx - my * dsxy;
+    coef[N + off] = dsxx;
+    coef[2 * N + off] = dsxy;
     ssum += S;
-    lsum += fabsf(sx[r + kR][c + kR] - sy[r + kR][c + kR]);
+    lsum += fabsf(sin_[0][r0 + o + kR][c + kR] - sin_[1][r0 + o + kR][c + kR]);
   }
   red[0][tid] = ssum;
   red[1][tid] = lsum;
@@ -247,9 +302,8 @@ __global__ __launch_bounds__(kBlock) void k_ssim_grad(const float *__restrict__ 
                                                       const float *__restrict__ y,
                                                       const float *__restrict__ coef, int n, int h,
                                                       int w, float lambda, float *__restrict__ grad) {
-  constexpr int IW = kSW + 2 * kR, IH = kSH + 2 * kR;
-  __shared__ float sd[3][IH][IW];
-  __shared__ float hz[3][IH][kSW];
+  __shared__ float sd[3][kIH][kIW];
+  __shared__ float hz[3][kIH][kSW];
   const int tiles_x = (w + kSW - 1) / kSW, tiles_y = (h + kSH - 1) / kSH;
   const int b = blockIdx.x;
   const int img = b / (tiles_x * tiles_y), tt = b - img * tiles_x * tiles_y;
@@ -258,44 +312,30 @@ __global__ __launch_bounds__(kBlock) void k_ssim_grad(const float *__restrict__ 
   const int64_t N = (int64_t)n * h * w;
   const int64_t ib = (int64_t)img * h * w;
   const int tid = threadIdx.x;
-  for (int i = tid; i < IW * IH; i += kBlock) {
-    const int r = i / IW, c = i - r * IW;
+  for (int i = tid; i < kIW * kIH; i += kBlock) {
+    const int r = i / kIW, c = i - r * kIW;
     const int gy = Y0 + r, gx = X0 + c;
     const bool in = gx >= 0 && gx < w && gy >= 0 && gy < h;
     const int64_t o = ib + (int64_t)gy * w + gx;
     for (int q = 0; q < 3; ++q) sd[q][r][c] = in ? coef[q * N + o] : 0.f;
   }
   __syncthreads();
-  for (int i = tid; i < IH * kSW; i += kBlock) {
-    const int r = i / kSW, c = i - r * kSW;
-    float a[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-    for (int k = 0; k < kWin; ++k) {
-      const float wk = c_win[k];
-#pragma unroll
-      for (int q = 0; q < 3; ++q) a[q] = fmaf(wk, sd[q][r][c + k], a[q]);
-    }
-    for (int q = 0; q < 3; ++q) hz[q][r][c] = a[q];
-  }
+  row_pass<3>(sd, hz);
   __syncthreads();
+  float m[3][kRB];
+  col_pass<3>(hz, m);
+  const int c = tid & (kSW - 1), r0 = (tid / kSW) * kRB;
   const float invN = 1.f / (float)N;
-  for (int i = tid; i < kSH * kSW; i += kBlock) {
-    const int r = i / kSW, c = i - r * kSW;
-    const int gy = ty * kSH + r, gx = tx * kSW + c;
+#pragma unroll
+  for (int o = 0; o < kRB; ++o) {
+    const int gy = ty * kSH + r0 + o, gx = tx * kSW + c;
     if (gx >= w || gy >= h) continue;
-    float m[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-    for (int k = 0; k < kWin; ++k) {
-      const float wk = c_win[k];
-#pragma unroll
-      for (int q = 0; q < 3; ++q) m[q] = fmaf(wk, hz[q][r + k][c], m[q]);
-    }
-    const int64_t o = ib + (int64_t)gy * w + gx;
-    const float xv = x[o], yv = y[o];
-    const float dssim = m[0] + 2.f * xv * m[1] + yv * m[2];
+    const int64_t off = ib + (int64_t)gy * w + gx;
+    const float xv = x[off], yv = y[off];
+    const float dssim = m[0][o] + 2.f * xv * m[1][o] + yv * m[2][o];
     const float d = xv - yv;
     const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
-    grad[o] = (sg - lambda * dssim) * invN;
+    grad[off] = (sg - lambda * dssim) * invN;
   }
 }
 

@@ -187,9 +187,12 @@ def test_backward_without_forward_and_accumulate(ops):
     c = tuple(x.clone() for x in b)
     ops.project_backward(*t, views, G, plan, 3.0, grads=c, accumulate=True)
     torch.cuda.synchronize()
+    # the backward sums per-block moments with LDS atomics: equal up to the
+    # order of FP32 additions
     for x, y, z in zip(a, b, c):
-        assert torch.equal(x, y)
-        assert torch.allclose(z, 2 * y, rtol=1e-6, atol=0)
+        scale = y.abs().max()
+        assert torch.allclose(x, y, rtol=1e-5, atol=1e-6 * float(scale))
+        assert torch.allclose(z, 2 * y, rtol=1e-5, atol=2e-6 * float(scale))
 
 
 # ----------------------------------------------------------------- losses --
@@ -287,7 +290,7 @@ def test_autograd_functions_match_direct_calls(ops):
     ops.project_forward(*d, views, 3.0, plan)
     ref = ops.project_backward(*d, views, G, plan, 3.0)
     for a, b in zip(t, ref):
-        assert torch.equal(a.grad, b)
+        assert torch.allclose(a.grad, b, rtol=1e-5, atol=1e-6 * float(b.abs().max()))
 
 
 # ----------------------------------------------------- full-size configs --
@@ -355,3 +358,114 @@ def test_training_iteration_matches_oracle_composition(ops):
     el, nr, det = parity.grad_violation(_np(grads), comb, rel=3e-3)
     print(det)
     assert el <= 1.0 and nr <= 1.0
+
+
+def _grad_subset(gpu, ref, sel):
+    sub_gpu = {k: gpu[k][sel] for k in KEYS}
+    sub_ref = {k: ref[k][sel] for k in KEYS}
+    sub_ref["S_abs"] = {k: ref["S_abs"][k][sel] for k in KEYS}
+    sub_ref["amb"] = {k: ref["amb"][k][sel] for k in KEYS}
+    return parity.grad_violation(sub_gpu, sub_ref)
+
+
+def test_c3_training_workload_full_size(ops):
+    """The measured workload at full size, in the launch configuration the
+    benchmark times (200k Gaussians, 75 views of 512^2 in one launch, a 64^3
+    TV block of the 256^3 grid): projection forward on three sampled views,
+    projection gradients of 32 sampled Gaussians with an upstream gradient on
+    those views, the full TV block forward and backward, and the loss terms on
+    the full 75-image stack."""
+    from paper_2405_20693_amd.iteration import TrainingIteration
+    wl = workloads.c3_iteration()
+    views = ops.Views.from_scan(wl.scan)
+    t = _dev(wl.gaussians)
+    plan = ops.Plan()
+    img = ops.project_forward(*t, views, 3.0, plan)
+    sel_v = [5, 40, 71]
+    G = np.zeros((75, 512, 512), np.float32)
+    G[sel_v] = upstream(2, (3, 512, 512))
+    grads = ops.project_backward(*t, views, torch.from_numpy(G).cuda(), plan, 3.0)
+    torch.cuda.synchronize()
+    ov = oracle.views_from_scan(wl.scan)
+    sub = [ov[i] for i in sel_v]
+    ref = oracle.project(wl.gaussians, sub)
+    v, _ = parity.forward_violation(img.cpu().numpy()[sel_v], ref)
+    _report("c3 forward (3 views)", v)
+    assert v <= 1.0
+    sel_g = np.random.default_rng(1).choice(wl.gaussians.n, 32, replace=False)
+    rg = oracle.project_grad(wl.gaussians, sub, G[sel_v], 3.0, select=sel_g, with_scale=True)
+    el, nr, det = _grad_subset(_np(grads), rg, sel_g)
+    print(det)
+    _report("c3 grads (32 Gaussians)", max(el, nr))
+    assert el <= 1.0 and nr <= 1.0
+    # TV block of the iteration: voxelization forward + backward in full
+    grid = workloads.tv_block_grid(wl, 0)
+    vplan = ops.Plan()
+    vol = ops.voxelize_forward(*t, ops.grid_from(grid), 3.0, vplan)
+    H = upstream(3, (64, 64, 64))
+    vg = ops.voxelize_backward(*t, ops.grid_from(grid), torch.from_numpy(H).cuda(), vplan, 3.0)
+    torch.cuda.synchronize()
+    vref = oracle.voxelize(wl.gaussians, grid)
+    vv, _ = parity.forward_violation(vol.cpu().numpy(), vref)
+    _report("c3 TV block voxelize", vv)
+    assert vv <= 1.0
+    touched = np.unique(np.random.default_rng(2).choice(wl.gaussians.n, 20000, replace=False))
+    vr = oracle.voxelize_grad(wl.gaussians, grid, H, 3.0, select=touched, with_scale=True)
+    nz_sel = touched[np.abs(vr["density"][touched]) > 0][:64]
+    if nz_sel.size:
+        el, nr, det = _grad_subset(_np(vg), vr, nz_sel)
+        _report(f"c3 TV block grads ({nz_sel.size} Gaussians)", max(el, nr))
+        assert el <= 1.0 and nr <= 1.0
+    # loss terms on the full stack (rendered image vs measured projections)
+    meas = workloads.measured_projections(wl)
+    rimg = img.cpu().numpy()
+    loss, lg = ops.image_loss(img, torch.from_numpy(meas).cuda(), ops.Plan(), 0.25)
+    torch.cuda.synchronize()
+    total, l1, s, gref = oracle.image_loss(rimg, meas, 0.25)
+    lv = loss.cpu().numpy()
+    assert abs(lv[1] - l1) <= 1e-5 * l1 and abs(lv[2] - s) <= 2e-5
+    gg = lg.cpu().numpy()
+    assert np.abs(gg - gref).max() <= 1e-3 * np.abs(gref).max()
+
+
+def test_c5_large_sampled(ops):
+    """1M anisotropic Gaussians, 150 cone views of 1024^2 in one launch and a
+    512^3 voxelization: forward on two sampled views, gradients of 24 sampled
+    Gaussians (upstream gradient on those views), and the volume on two
+    sampled 24^3 sub-blocks."""
+    wl = workloads.c5_large()
+    views = ops.Views.from_scan(wl.scan)
+    t = _dev(wl.gaussians)
+    plan = ops.Plan()
+    img = ops.project_forward(*t, views, 3.0, plan)
+    sel_v = [17, 104]
+    G = torch.zeros((150, 1024, 1024), device="cuda")
+    Gs = upstream(4, (2, 1024, 1024))
+    G[sel_v] = torch.from_numpy(Gs).cuda()
+    grads = ops.project_backward(*t, views, G, plan, 3.0)
+    torch.cuda.synchronize()
+    st = plan.status()
+    print("c5 tile entries", st["tile_entries"], flush=True)
+    img_s = img[sel_v].cpu().numpy()
+    del img, G
+    ov = oracle.views_from_scan(wl.scan)
+    sub = [ov[i] for i in sel_v]
+    ref = oracle.project(wl.gaussians, sub)
+    v, _ = parity.forward_violation(img_s, ref)
+    _report("c5 forward (2 views)", v)
+    assert v <= 1.0
+    sel_g = np.random.default_rng(5).choice(wl.gaussians.n, 24, replace=False)
+    rg = oracle.project_grad(wl.gaussians, sub, Gs, 3.0, select=sel_g, with_scale=True)
+    el, nr, det = _grad_subset(_np(grads), rg, sel_g)
+    print(det)
+    _report("c5 grads (24 Gaussians)", max(el, nr))
+    assert el <= 1.0 and nr <= 1.0
+    vol = ops.voxelize_forward(*t, ops.grid_from(wl.grid), 3.0, ops.Plan())
+    torch.cuda.synchronize()
+    for (i0, j0, k0) in [(240, 250, 244), (100, 300, 380)]:
+        sg = workloads.sub_grid(wl.grid, i0, j0, k0, 24, 24, 24)
+        vr = oracle.voxelize(wl.gaussians, sg)
+        part = vol[k0:k0 + 24, j0:j0 + 24, i0:i0 + 24].cpu().numpy()
+        vv, _ = parity.forward_violation(part, vr)
+        _report(f"c5 volume block {(i0, j0, k0)}", vv)
+        assert vv <= 1.0

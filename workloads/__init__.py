@@ -250,6 +250,34 @@ def c3_iteration(seed=0, m=200_000, n_views=75, det=512, pitch_mm=0.75, full=256
                     extra={"ellipsoids": ells, "full": full, "block": block})
 
 
+def c5_large(seed=0, m=1_000_000, n_views=150, det=1024, pitch_mm=0.375, vol=512):
+    """1,000,000 Gaussians on the 12-ellipsoid phantom with prolate,
+    volume-preserving anisotropy up to 20:1 (r ~ exp(U[0, ln 20]), scales
+    sigma_NN (r^(2/3), r^(-1/3), r^(-1/3))), 150 cone views of 1024^2 at
+    0.375 mm, a 512^3 grid over [-1,1]^3."""
+    rng = np.random.default_rng(seed)
+    ells = ellipsoids_shepp_logan_style(rng)
+    p = rejection_sample(rng, ells, m, 0.05, clip=True, box=False, batch=1_000_000)
+    f = phantom_value(ells, p, clip=True)
+    r = np.exp(rng.uniform(0.0, math.log(20.0), m))
+    s = nn_scale(p)[:, None] * np.stack([r ** (2 / 3), r ** (-1 / 3), r ** (-1 / 3)], 1)
+    q = random_quats(rng, m)
+    rho = 0.15 * f
+    g = Gaussians(_f32(p), _f32(s), _f32(q), _f32(rho))
+    scan = cone_scan(n_views, det, det, pitch_mm)
+    h = 2.0 / vol
+    grid = Grid(vol, vol, vol, (-1.0, -1.0, -1.0), (h, h, h))
+    return Workload(f"c5_large_{m // 1000}k_{n_views}x{det}px_vox{vol}", g, scan, grid,
+                    extra={"ellipsoids": ells})
+
+
+def sub_grid(grid: Grid, i0, j0, k0, nx, ny, nz) -> Grid:
+    """The voxels [k0:k0+nz, j0:j0+ny, i0:i0+nx] of `grid` as a grid of their own."""
+    h = grid.spacing
+    o = grid.origin
+    return Grid(nx, ny, nz, (o[0] + i0 * h[0], o[1] + j0 * h[1], o[2] + k0 * h[2]), h)
+
+
 def tv_block_grid(wl: Workload, iteration: int) -> Grid:
     """Random D^3 sub-block of the full TV grid at the target spacing; the
     offset is drawn with seed = iteration."""
