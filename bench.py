@@ -60,12 +60,90 @@ def cpu_baseline(wl, measured, target_s=15.0):
                       f"{t_views + t_vox:.1f} s"}
 
 
+def serving(args):
+    """Served renders/s and p50/p99 latency for 16 resident models (20k-500k
+    Gaussians) under Poisson arrivals, continuous batching (4 workers, merged
+    same-model projections) against the plain per-request path (one request
+    per launch, one at a time), on the same arrival traces."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2405_20693_amd import ops
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log("generating 16 models ...")
+    models = [[torch.from_numpy(a).to(dev) for a in (m.mean, m.scale, m.quat, m.density)]
+              for m in workloads.c4_models()]
+    servers = {"continuous": ops.Server(n_workers=4, batching=True, max_batch_views=256),
+               "per_request": ops.Server(n_workers=1, batching=False)}
+    for srv in servers.values():
+        for m in models:
+            srv.add_model(*m)
+
+    def trace(seed, n, rate):
+        reqs = []
+        for r in workloads.c4_requests(seed, n, rate):
+            d = {"kind": r["kind"], "model": r["model"], "arrival_s": r["arrival_s"]}
+            if r["kind"] == "project":
+                d["views"] = ops.Views.from_scan(r["scan"])
+            else:
+                d["grid"] = ops.grid_from(r["grid"])
+            reqs.append(d)
+        return reqs
+
+    def summarize(reqs, res, wall):
+        lat = np.array([x["latency_s"] for x in res]) * 1e3
+        views = sum(r["views"].n for r in reqs if r["kind"] == "project")
+        vols = sum(1 for r in reqs if r["kind"] == "volume")
+        return {"renders_per_s": round(views / wall, 1), "volumes_per_s": round(vols / wall, 2),
+                "requests_per_s": round(len(reqs) / wall, 2),
+                "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                "p99_ms": round(float(np.percentile(lat, 99)), 2),
+                "mean_batch": round(float(np.mean([x["batch_size"] for x in res])), 2)}
+
+    warm = trace(7, 48, 0.0)
+    for srv in servers.values():
+        srv.run(warm, time_scale=0.0)
+    torch.cuda.synchronize()
+    n_sat = args.serving_requests
+    sat = {}
+    for name, srv in servers.items():
+        reqs = trace(3, n_sat, 0.0)
+        res, wall = srv.run(reqs, time_scale=0.0)
+        sat[name] = summarize(reqs, res, wall)
+        log(f"saturation {name}: {sat[name]}")
+    cap = sat["continuous"]["requests_per_s"]
+    loads = {}
+    for frac in (0.1, 0.3, 0.6, 0.9, 1.2):
+        rate = frac * cap
+        reqs = trace(11, n_sat, rate)
+        row = {"rate_req_per_s": round(rate, 2)}
+        for name, srv in servers.items():
+            res, wall = srv.run(reqs, time_scale=1.0)
+            row[name] = summarize(reqs, res, wall)
+        loads[f"{frac:.1f}x"] = row
+        log(f"load {frac:.1f}x: {row}")
+    out = {"metric": "served renders/s + p99 (16 resident models 20k-500k, Poisson arrivals)",
+           "value": sat["continuous"]["renders_per_s"], "unit": "renders/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "c4_serving_16_models_20k-500k", "requests_per_point": n_sat,
+                      "mix": "80% projections (1-64 views, 256^2@1.5mm or 512^2@0.75mm), "
+                             "20% 128^3 sub-volumes of a 256^3 grid",
+                      "continuous": "4 workers (streams), same-model projection merging up to 256 views",
+                      "per_request": "1 worker, one request per launch"},
+           "saturation": sat, "loads": loads}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving", action="store_true",
+                    help="measure the serving loop instead of the training iteration")
+    ap.add_argument("--serving-requests", type=int, default=1000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device (a reference kernel of known "
                          "traffic for scaling HBM counters)")
@@ -83,6 +161,9 @@ def main():
     from paper_2405_20693_amd.iteration import TrainingIteration
 
     lib()  # fails loudly if the HIP library is not built
+    if args.serving:
+        serving(args)
+        return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.calibrate_copy:

@@ -40,6 +40,22 @@ class GsGrads(ctypes.Structure):
     _fields_ = [("mean", c_void_p), ("scale", c_void_p), ("quat", c_void_p), ("density", c_void_p)]
 
 
+class GsServerConfig(ctypes.Structure):
+    _fields_ = [("n_workers", c_int32), ("batching", c_int32), ("max_batch_views", c_int32),
+                ("cutoff", c_float), ("hbm_budget_bytes", c_int64)]
+
+
+class GsRequest(ctypes.Structure):
+    _fields_ = [("kind", c_int32), ("model", c_int32), ("arrival_s", c_double),
+                ("n_views", c_int32), ("views", ctypes.POINTER(GsView)), ("grid", GsGrid),
+                ("out", c_void_p)]
+
+
+class GsRequestResult(ctypes.Structure):
+    _fields_ = [("start_s", c_double), ("done_s", c_double), ("latency_s", c_double),
+                ("batch_size", c_int32), ("status", c_int32)]
+
+
 class GsError(RuntimeError):
     def __init__(self, func, status, message):
         self.status = status
@@ -72,6 +88,12 @@ EXPORTS = {
     "gs_plan_stage_times": (ctypes.c_int, [c_void_p, ctypes.POINTER(c_double),
                                            ctypes.POINTER(c_int64), c_int32]),
     "gs_last_error": (ctypes.c_char_p, []),
+    "gs_server_create": (ctypes.c_int, [ctypes.POINTER(GsServerConfig), ctypes.POINTER(c_void_p)]),
+    "gs_server_destroy": (None, [c_void_p]),
+    "gs_server_add_model": (ctypes.c_int, [c_void_p, ctypes.POINTER(GsGaussians),
+                                           ctypes.POINTER(c_int32)]),
+    "gs_server_run": (ctypes.c_int, [c_void_p, ctypes.POINTER(GsRequest), c_int64, c_double,
+                                     ctypes.POINTER(GsRequestResult), ctypes.POINTER(c_double)]),
 }
 
 

@@ -273,3 +273,73 @@ def project(mean, scale, quat, density, views: Views, cutoff=3.0, plan=None):
 def voxelize(mean, scale, quat, density, grid, cutoff=3.0, plan=None):
     """Differentiable voxelization [nz, ny, nx] (HIP forward and backward)."""
     return _Voxelize.apply(mean, scale, quat, density, grid, cutoff, plan or Plan())
+
+
+# ---------------------------------------------------------------- serving --
+
+class Server:
+    """Request loop of include/gs_serve.h: worker threads with their own
+    streams and plans, merging of same-model projection requests, admission
+    by an estimated device-memory budget.  All work runs in libgs.so."""
+
+    def __init__(self, n_workers=4, batching=True, max_batch_views=128, cutoff=3.0,
+                 hbm_budget_bytes=None):
+        if hbm_budget_bytes is None:
+            free, _ = torch.cuda.mem_get_info()
+            hbm_budget_bytes = int(0.5 * free)
+        cfg = N.GsServerConfig(int(n_workers), int(bool(batching)), int(max_batch_views),
+                               float(cutoff), int(hbm_budget_bytes))
+        h = ctypes.c_void_p()
+        N.call("gs_server_create", ctypes.byref(cfg), ctypes.byref(h))
+        self._h = h
+        self._models = []
+
+    def add_model(self, mean, scale, quat, density):
+        g = _gaussians(mean, scale, quat, density)
+        mid = ctypes.c_int32()
+        N.call("gs_server_add_model", self._h, ctypes.byref(g), ctypes.byref(mid))
+        self._models.append((mean, scale, quat, density))  # keep the tensors alive
+        return mid.value
+
+    def run(self, requests, time_scale=1.0):
+        """requests: list of dicts with kind ('project' | 'volume'), model,
+        arrival_s, and views (Views) or grid (gs_grid), optional out tensor.
+        Returns (list of result dicts, wall seconds)."""
+        n = len(requests)
+        arr = (N.GsRequest * n)()
+        keep = []
+        for i, r in enumerate(requests):
+            q = arr[i]
+            q.model = int(r["model"])
+            q.arrival_s = float(r["arrival_s"])
+            out = r.get("out")
+            if r["kind"] == "project":
+                q.kind = 0
+                q.n_views = r["views"].n
+                q.views = ctypes.cast(r["views"].arr, ctypes.POINTER(N.GsView))
+                keep.append(r["views"])
+                if out is not None:
+                    _dev(out, "out", (r["views"].n, r["views"].height, r["views"].width))
+            else:
+                q.kind = 1
+                q.grid = r["grid"]
+                if out is not None:
+                    _dev(out, "out", (r["grid"].nz, r["grid"].ny, r["grid"].nx))
+            q.out = _ptr_or_null(out)
+        res = (N.GsRequestResult * n)()
+        wall = ctypes.c_double()
+        N.call("gs_server_run", self._h, arr, n, float(time_scale), res, ctypes.byref(wall))
+        out = [{"start_s": x.start_s, "done_s": x.done_s, "latency_s": x.latency_s,
+                "batch_size": x.batch_size, "status": x.status} for x in res]
+        return out, wall.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            N.lib().gs_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -278,6 +278,49 @@ def sub_grid(grid: Grid, i0, j0, k0, nx, ny, nz) -> Grid:
     return Grid(nx, ny, nz, (o[0] + i0 * h[0], o[1] + j0 * h[1], o[2] + k0 * h[2]), h)
 
 
+def phantom_model(seed, m, tau=0.05, jitter=0.3):
+    """A resident model for serving: C3-style phantom Gaussians (seeded)."""
+    rng = np.random.default_rng(seed)
+    ells = ellipsoids_shepp_logan_style(rng)
+    p = rejection_sample(rng, ells, m, tau, clip=True, box=False)
+    f = phantom_value(ells, p, clip=True)
+    s = nn_scale(p)[:, None] * np.exp(rng.uniform(-jitter, jitter, (m, 3)))
+    q = random_quats(rng, m)
+    return Gaussians(_f32(p), _f32(s), _f32(q), _f32(0.15 * f))
+
+
+def c4_models(seed=0, n_models=16, lo=20_000, hi=500_000):
+    """Sizes log-uniform in [20k, 500k] (seed 0); model j from seed 1000 + j."""
+    rng = np.random.default_rng(seed)
+    sizes = np.round(np.exp(rng.uniform(math.log(lo), math.log(hi), n_models))).astype(int)
+    return [phantom_model(1000 + j, int(m)) for j, m in enumerate(sizes)]
+
+
+def c4_requests(seed, n, rate, n_models=16, full=256, block=128):
+    """Poisson arrivals at `rate` requests/s.  80% projections: 1-64 views
+    evenly spaced from a random start angle, 256^2 at 1.5 mm or 512^2 at
+    0.75 mm (p = 1/2); 20% volume queries: a 128^3 block of the 256^3 grid over
+    [-1,1]^3 at offset U{0..128}^3."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, n)) if rate > 0 else np.zeros(n)
+    out = []
+    h = 2.0 / full
+    for i in range(n):
+        model = int(rng.integers(0, n_models))
+        if rng.uniform() < 0.8:
+            nv = int(rng.integers(1, 65))
+            th0 = rng.uniform(0.0, 2 * math.pi)
+            det, pitch = (256, 1.5) if rng.uniform() < 0.5 else (512, 0.75)
+            scan = cone_scan(nv, det, det, pitch)
+            scan.thetas = th0 + scan.thetas
+            out.append({"kind": "project", "model": model, "arrival_s": float(t[i]), "scan": scan})
+        else:
+            off = rng.integers(0, full - block + 1, 3)
+            g = Grid(block, block, block, tuple(float(-1.0 + o * h) for o in off), (h, h, h))
+            out.append({"kind": "volume", "model": model, "arrival_s": float(t[i]), "grid": g})
+    return out
+
+
 def tv_block_grid(wl: Workload, iteration: int) -> Grid:
     """Random D^3 sub-block of the full TV grid at the target spacing; the
     offset is drawn with seed = iteration."""
