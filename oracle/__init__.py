@@ -213,6 +213,14 @@ def project_gaussians(mean, scale, quat, density, view):
             "Sigma_hat": Sig_h, "Sigma_tilde": Sig_t, "t": t, "ok": ok}
 
 
+def _unrectify(pr, density):
+    """The unrectified (3DGS-style) reading of Sec. 3.2.1 "Integration bias":
+    the 2D Gaussian keeps the 3D central density, rho_hat = rho."""
+    pr = dict(pr)
+    pr["rho_hat"] = density * torch.ones_like(pr["rho_hat"])
+    return pr
+
+
 def _rec2d_array(pr, kappa):
     ok = pr["ok"].detach().numpy()
     A00, A01, A11 = (a.detach().numpy() for a in pr["A"])
@@ -243,7 +251,7 @@ def _check_views(views):
 # Projection (X-ray rasterization)
 # ---------------------------------------------------------------------------
 
-def project(g, views, cutoff=3.0, brute=False):
+def project(g, views, cutoff=3.0, brute=False, rectify=True):
     """Rendered projections I_r[v][b][a] (Eq. 7): sum over Gaussians of
     rho_hat exp(-q/2), q the Mahalanobis distance of the pixel centre under the
     projected covariance, terms with q <= cutoff^2 only (cutoff = inf keeps all).
@@ -257,7 +265,10 @@ def project(g, views, cutoff=3.0, brute=False):
     rec = np.zeros((nv, n, 9))
     with torch.no_grad():
         for v, view in enumerate(views):
-            rec[v] = _rec2d_array(project_gaussians(*params, view), cutoff)
+            pr = project_gaussians(*params, view)
+            if not rectify:
+                pr = _unrectify(pr, params[3])
+            rec[v] = _rec2d_array(pr, cutoff)
     img = np.zeros((nv, height, width))
     S = np.zeros_like(img)
     amb = np.zeros_like(img)
@@ -277,7 +288,8 @@ def _rec2d_tensors(pr):
             pr["rho_hat"] * m]
 
 
-def project_grad(g, views, grad_image, cutoff=3.0, brute=False, select=None, with_scale=False):
+def project_grad(g, views, grad_image, cutoff=3.0, brute=False, select=None, with_scale=False,
+                 rectify=True):
     """Gradient of L = sum G * I_r with respect to mean, scale, quat
     (unnormalised), density.  The cutoff indicator is treated as locally
     constant (its derivative is zero almost everywhere).
@@ -303,6 +315,8 @@ def project_grad(g, views, grad_image, cutoff=3.0, brute=False, select=None, wit
     pix = _pix(views)
     for v, view in enumerate(views):
         pr = project_gaussians(*params, view)
+        if not rectify:
+            pr = _unrectify(pr, params[3])
         rec = _rec2d_array(pr, cutoff)
         d = np.zeros((n, 6))
         da = np.zeros((n, 6)) if with_scale else None
@@ -330,6 +344,23 @@ def project_grad(g, views, grad_image, cutoff=3.0, brute=False, select=None, wit
         res["S_abs"] = {k: t.detach().numpy() for k, t in sabs.items()}
         res["amb"] = {k: t.detach().numpy() for k, t in samb.items()}
     return res
+
+
+def mean_mu(g, views):
+    """Mean over the views of each Gaussian's rectification factor
+    mu = sqrt(2 pi |Sigma_tilde| / |Sigma_hat|) (views where it is culled are
+    left out; 0 if culled in all); the X-3DGS correction divides the densities
+    of an unrectified model by it before voxelization (Sec. 4.3)."""
+    params = _params(g)
+    tot = np.zeros(g.n)
+    cnt = np.zeros(g.n)
+    with torch.no_grad():
+        for view in views:
+            pr = project_gaussians(*params, view)
+            ok = pr["ok"].numpy()
+            tot[ok] += pr["mu"].numpy()[ok]
+            cnt[ok] += 1
+    return np.where(cnt > 0, tot / np.maximum(cnt, 1), 0.0)
 
 
 # ---------------------------------------------------------------------------

@@ -23,6 +23,20 @@ def random_scene(seed, m, lo=0.05, hi=0.2, box=0.5, rho=(0.5, 1.0)):
     return gaussians(mean, scale, q, dens)
 
 
+def lattice(seed=7, rot_seed=3, n_side=3, spacing=0.3):
+    """Strongly anisotropic Gaussians (axis ratios up to 8:1) on a jittered
+    cubic lattice, densities in [0.5, 1]."""
+    rng = np.random.default_rng(seed)
+    m = n_side ** 3
+    ax = (np.arange(n_side) - (n_side - 1) / 2) * spacing
+    mean = np.stack(np.meshgrid(ax, ax, ax, indexing="ij"), -1).reshape(-1, 3)
+    mean = mean + rng.uniform(-0.03, 0.03, (m, 3))
+    scale = np.stack([rng.uniform(0.02, 0.04, m), rng.uniform(0.04, 0.08, m),
+                      rng.uniform(0.1, 0.16, m)], 1)
+    q = Rotation.random(m, random_state=rot_seed).as_quat()[:, [3, 0, 1, 2]]
+    return gaussians(mean, scale, q, rng.uniform(0.5, 1.0, m))
+
+
 def scipy_covariance(g):
     """Sigma = R diag(s^2) R^T with R from scipy (Hamilton, active); quaternions
     are stored (w,x,y,z) and scipy takes (x,y,z,w)."""

@@ -7,6 +7,7 @@ the oracle (dropped rectification factor, wrong sign in the scanner rotation,
 transposed rotation, wrong Jacobian row, wrong pixel centre) fails at least one
 of them.  No GPU is used.
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -491,3 +492,74 @@ def test_pin_catches_wrong_third_jacobian_row(monkeypatch):
     monkeypatch.setattr(oracle, "project_gaussians", axis_row)
     with pytest.raises(AssertionError):
         test_cone_central_ray_equals_exact_integral(0.9)
+
+
+# ------------------------------------------------ integration bias (P13) ---
+
+def test_unrectified_projection_is_biased_by_mu():
+    """Parallel beam: the unrectified image times mu equals the exact line
+    integral (so the unrectified image is the integral divided by a
+    view-dependent factor)."""
+    g = scenes.gaussians([[0.05, -0.1, 0.2]], [[0.06, 0.2, 0.1]], [[0.7, 0.1, -0.4, 0.3]], [0.9])
+    rot = Rotation.random(random_state=12).as_matrix()
+    view = oracle.parallel_view(rot, 40, 40, 0.03)
+    unrect = oracle.project(g, [view], cutoff=INF, rectify=False)["image"][0]
+    rect = oracle.project(g, [view], cutoff=INF)["image"][0]
+    mu = oracle.mean_mu(g, [view])[0]
+    np.testing.assert_allclose(unrect * mu, rect, rtol=1e-12, atol=1e-15)
+    W = view["W"]
+    u, v = scenes.pixel_centres(view)
+    o = u[None, :, None] * W[0] + v[:, None, None] * W[1]
+    exact = scenes.line_integral(g, o, np.broadcast_to(W[2] / np.linalg.norm(W[2]), o.shape))
+    np.testing.assert_allclose(unrect * mu, exact, rtol=1e-6, atol=1e-8 * exact.max())
+
+
+def test_rectification_gives_view_consistent_density():
+    """The density recovered from each view's central pixel, I_j(p_hat_j) /
+    mu_j, is the same 3D density for every view with rectification; an
+    unrectified renderer would need a different density per view (mu_j varies
+    with the view for an anisotropic Gaussian)."""
+    views, mus, peaks = [], [], []
+    for th in np.linspace(0.0, np.pi, 7):
+        view = oracle.cone_view(th, 13.64, 20.46, 48, 40, 0.06)
+        g, o, d = _on_ray_gaussian(view, th, 30, 11, 13.0, [0.04, 0.2, 0.08], [0.9, -0.2, 0.35, 0.1], 0.8)
+        img = oracle.project(g, [view], cutoff=INF)["image"][0]
+        peaks.append(img[11, 30])
+        mus.append(oracle.mean_mu(g, [view])[0])
+    ratio = np.array(peaks) / np.array(mus)
+    np.testing.assert_allclose(ratio, 0.8, rtol=2e-6)
+    mus = np.array(mus)
+    assert mus.std() / mus.mean() > 0.1
+
+
+def test_integration_bias_least_squares():
+    """Sec. 3.2.1 / Sec. 4.3 on a synthetic phantom: fit only the densities of
+    a model whose geometry is exact to projections of that model.  Rectified
+    kernels recover the true densities exactly (the data lie in their range);
+    the unrectified kernels cannot fit all views with one density per Gaussian,
+    their density divided by the mean mu is wrong, and dividing by each view's
+    mu_j gives a different density per view."""
+    g = scenes.lattice()
+    views = [oracle.cone_view(t, 13.64, 20.46, 32, 32, 0.06)
+             for t in np.linspace(0, np.pi, 6, endpoint=False)]
+
+    def footprints(rectify):
+        cols = []
+        for i in range(g.n):
+            d = np.zeros(g.n, np.float32)
+            d[i] = 1.0
+            gi = dataclasses.replace(g, density=d)
+            cols.append(oracle.project(gi, views, rectify=rectify)["image"].ravel())
+        return np.stack(cols, 1)
+
+    rho = g.density.astype(np.float64)
+    A_rect, A_un = footprints(True), footprints(False)
+    b = A_rect @ rho
+    fit_rect = np.linalg.lstsq(A_rect, b, rcond=None)[0]
+    np.testing.assert_allclose(fit_rect, rho, atol=1e-9)
+    fit_un = np.linalg.lstsq(A_un, b, rcond=None)[0]
+    assert np.linalg.norm(A_un @ fit_un - b) / np.linalg.norm(b) > 0.05
+    mubar = oracle.mean_mu(g, views)
+    assert np.linalg.norm(fit_un / mubar - rho) / np.linalg.norm(rho) > 0.05
+    per_view = fit_un[None] / np.stack([oracle.mean_mu(g, [v]) for v in views])
+    assert np.median((per_view.max(0) - per_view.min(0)) / rho) > 0.2
