@@ -346,6 +346,49 @@ def project_grad(g, views, grad_image, cutoff=3.0, brute=False, select=None, wit
     return res
 
 
+def grad2d(g, views, grad_image, cutoff=3.0, rectify=True):
+    """Per (view, Gaussian): the gradient of L = sum G * I_r with respect to
+    the projected centre p_hat (detector units, [V][n][2]) and whether the
+    Gaussian is visible in the view.  Visible reading (the screen-space
+    statistic of the adaptive control that Sec. 3.3 takes from 3DGS): some
+    pixel centre lies inside the axis-aligned bounding box of the cutoff
+    ellipse, |u - u_hat| <= kappa sqrt(Sigma_hat_uu) and |v - v_hat| <=
+    kappa sqrt(Sigma_hat_vv).  ambiguous marks views where moving the box
+    edges by 2e-3 pixel changes that answer."""
+    lib = _load()
+    width, height = _check_views(views)
+    nv, n = len(views), g.n
+    G = np.ascontiguousarray(np.asarray(grad_image, np.float64))
+    params = _params(g)
+    pix = _pix(views)
+    gp = np.zeros((nv, n, 2))
+    vis = np.zeros((nv, n), bool)
+    amb = np.zeros((nv, n), bool)
+    with torch.no_grad():
+        for v, view in enumerate(views):
+            pr = project_gaussians(*params, view)
+            if not rectify:
+                pr = _unrectify(pr, params[3])
+            rec = _rec2d_array(pr, cutoff)
+            d = np.zeros((n, 6))
+            lib.orc_splat2d_bwd(1, n, _ptr(rec), width, height, _ptr(pix[v:v + 1]), float(cutoff),
+                                0, _ptr(G[v]), None, _ptr(d), None, None)
+            gp[v] = d[:, 0:2]
+            hu, hv, ou, ov = pix[v]
+            u = (np.arange(width) + 0.5 - width / 2) * hu + ou
+            vv = (np.arange(height) + 0.5 - height / 2) * hv + ov
+            ok = rec[:, 8] > 0
+
+            def inside(margin):
+                du = np.abs(u[None, :] - rec[:, 0:1]) <= rec[:, 6:7] + margin * hu
+                dv = np.abs(vv[None, :] - rec[:, 1:2]) <= rec[:, 7:8] + margin * hv
+                return ok & du.any(1) & dv.any(1)
+
+            vis[v] = inside(0.0)
+            amb[v] = inside(2e-3) != inside(-2e-3)
+    return {"grad": gp, "visible": vis, "ambiguous": amb}
+
+
 def mean_mu(g, views):
     """Mean over the views of each Gaussian's rectification factor
     mu = sqrt(2 pi |Sigma_tilde| / |Sigma_hat|) (views where it is culled are
