@@ -190,6 +190,25 @@ GS_API gs_status gs_loss_tv(const float *volume, int32_t nx, int32_t ny, int32_t
                      float *loss_out, float *grad, int32_t accumulate, gs_plan *plan,
                      hipStream_t stream);
 
+/* Choose the projection's density scaling for later calls on this plan:
+ * enable = 1 (default) renders the rectified density rho_hat = mu rho of
+ * Eq. 7, mu = sqrt(2 pi |Sigma_tilde| / |Sigma_hat|); enable = 0 renders
+ * rho_hat = rho, the 3DGS-style unrectified reading whose integration bias the
+ * paper analyses (Sec. 3.2.1 "Integration bias"; the X-3DGS baseline of
+ * Sec. 4.3).  gs_project_bwd differentiates whichever was chosen. */
+GS_API gs_status gs_plan_set_rectify(gs_plan *plan, int32_t enable);
+
+/* Per-Gaussian mean over the views of the rectification factor mu (views in
+ * which the Gaussian is culled are left out; 0 if culled in all).  Dividing an
+ * unrectified model's densities by it is the paper's correction of X-3DGS
+ * before voxelization (Sec. 4.3).  mu_out: device [n] or NULL; density_out:
+ * device [n] or NULL, receives density / mean mu (0 where the mean is 0).  At
+ * least one of the two must be given (else GS_EINVAL).  The plan's view buffer
+ * is reused, so the next projection call on the plan bins again. */
+GS_API gs_status gs_project_mean_mu(const gs_gaussians *g, const gs_view *views, int32_t n_views,
+                                    float *mu_out, float *density_out, gs_plan *plan,
+                                    hipStream_t stream);
+
 /* Stages of the launch sequences, for gs_plan_stage_times. */
 typedef enum {
   GS_STAGE_PROJ_BIN = 0,     /* projection + rectification, tile histograms, scans */

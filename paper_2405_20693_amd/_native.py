@@ -56,6 +56,40 @@ class GsRequestResult(ctypes.Structure):
                 ("batch_size", c_int32), ("status", c_int32)]
 
 
+class GsGradStats(ctypes.Structure):
+    _fields_ = [("grad_sum", c_void_p), ("visible", c_void_p), ("scale", c_float)]
+
+
+PARAM_FIELDS = ("mean", "log_scale", "quat", "density_raw", "scale", "density",
+                "m_mean", "m_scale", "m_quat", "m_density", "v_mean", "v_scale", "v_quat",
+                "v_density")
+
+
+class GsParams(ctypes.Structure):
+    _fields_ = [(f, c_void_p) for f in PARAM_FIELDS]
+
+
+class GsAdamConfig(ctypes.Structure):
+    _fields_ = [("lr_mean", c_float), ("lr_scale", c_float), ("lr_quat", c_float),
+                ("lr_density", c_float), ("step", c_int32)]
+
+
+class GsDensifyConfig(ctypes.Structure):
+    _fields_ = [("grad_threshold", c_float), ("clone_max_scale", c_float),
+                ("min_density", c_float), ("densify", c_int32)]
+
+
+class GsTrainConfig(ctypes.Structure):
+    _fields_ = [("iterations", c_int32), ("views_per_iter", c_int32),
+                ("lr_mean", c_float), ("lr_density", c_float), ("lr_scale", c_float),
+                ("lr_quat", c_float), ("lr_final_ratio", c_float), ("lambda_ssim", c_float),
+                ("lambda_tv", c_float), ("tv_size", c_int32), ("densify_from", c_int32),
+                ("densify_until", c_int32), ("densify_interval", c_int32),
+                ("grad_threshold", c_float), ("clone_max_scale", c_float),
+                ("min_density", c_float), ("cutoff", c_float), ("rectify", c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
 class GsError(RuntimeError):
     def __init__(self, func, status, message):
         self.status = status
@@ -85,6 +119,9 @@ EXPORTS = {
     "gs_loss_tv": (ctypes.c_int, [c_void_p, c_int32, c_int32, c_int32, c_float, c_void_p, c_void_p,
                                   c_int32, c_void_p, c_void_p]),
     "gs_plan_set_timing": (ctypes.c_int, [c_void_p, c_int32]),
+    "gs_plan_set_rectify": (ctypes.c_int, [c_void_p, c_int32]),
+    "gs_project_mean_mu": (ctypes.c_int, [ctypes.POINTER(GsGaussians), ctypes.POINTER(GsView),
+                                          c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "gs_plan_stage_times": (ctypes.c_int, [c_void_p, ctypes.POINTER(c_double),
                                            ctypes.POINTER(c_int64), c_int32]),
     "gs_last_error": (ctypes.c_char_p, []),
@@ -94,6 +131,38 @@ EXPORTS = {
                                            ctypes.POINTER(c_int32)]),
     "gs_server_run": (ctypes.c_int, [c_void_p, ctypes.POINTER(GsRequest), c_int64, c_double,
                                      ctypes.POINTER(GsRequestResult), ctypes.POINTER(c_double)]),
+    # gs_train.h
+    "gs_project_bwd_stats": (ctypes.c_int, [ctypes.POINTER(GsGaussians), ctypes.POINTER(GsView),
+                                            c_int32, c_float, c_void_p, ctypes.POINTER(GsGrads),
+                                            c_int32, ctypes.POINTER(GsGradStats), c_void_p,
+                                            c_void_p]),
+    "gs_adam_step": (ctypes.c_int, [ctypes.POINTER(GsParams), c_int64, ctypes.POINTER(GsGrads),
+                                    ctypes.POINTER(GsAdamConfig), c_void_p]),
+    "gs_params_activate": (ctypes.c_int, [ctypes.POINTER(GsParams), c_int64, c_void_p]),
+    "gs_params_from_activated": (ctypes.c_int, [ctypes.POINTER(GsParams), c_int64, c_void_p]),
+    "gs_densify": (ctypes.c_int, [ctypes.POINTER(GsParams), c_int64, ctypes.POINTER(GsGradStats),
+                                  c_void_p, ctypes.POINTER(GsDensifyConfig),
+                                  ctypes.POINTER(GsParams), c_int64, c_void_p,
+                                  ctypes.POINTER(c_int64), c_void_p, c_void_p]),
+    "gs_volume_metrics": (ctypes.c_int, [c_void_p, c_void_p, c_int32, c_int32, c_int32,
+                                         ctypes.POINTER(c_double), ctypes.POINTER(c_double),
+                                         c_void_p, c_void_p]),
+    "gs_train_config_default": (None, [ctypes.POINTER(GsTrainConfig)]),
+    "gs_trainer_create": (ctypes.c_int, [ctypes.POINTER(GsTrainConfig), ctypes.POINTER(GsGaussians),
+                                         c_void_p, ctypes.POINTER(GsView), c_int32,
+                                         ctypes.POINTER(GsGrid), ctypes.POINTER(c_void_p)]),
+    "gs_trainer_destroy": (None, [c_void_p]),
+    "gs_trainer_run": (ctypes.c_int, [c_void_p, c_int32, c_void_p]),
+    "gs_trainer_step": (ctypes.c_int, [c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
+                                       c_void_p, ctypes.POINTER(c_float)]),
+    "gs_trainer_model": (ctypes.c_int, [c_void_p, ctypes.POINTER(GsGaussians),
+                                        ctypes.POINTER(c_int32)]),
+    "gs_trainer_export": (ctypes.c_int, [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
+                                         ctypes.POINTER(c_int64)]),
+    "gs_trainer_state": (ctypes.c_int, [c_void_p, ctypes.POINTER(GsParams), ctypes.POINTER(c_int64),
+                                        ctypes.POINTER(GsGradStats)]),
+    "gs_trainer_evaluate": (ctypes.c_int, [c_void_p, ctypes.POINTER(GsGrid), c_void_p, c_void_p,
+                                           ctypes.POINTER(c_double), ctypes.POINTER(c_double)]),
 }
 
 

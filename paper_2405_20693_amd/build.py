@@ -5,7 +5,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["api.hip", "project.hip", "voxel.hip", "scan_loss.hip", "serve.hip"]
+SOURCES = ["api.hip", "project.hip", "voxel.hip", "scan_loss.hip", "serve.hip", "train.hip",
+           "trainer.hip"]
 LIB = os.path.join(HERE, "libgs.so")
 
 FLAGS = [

@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "../../include/gs.h"
+#include "../../include/gs_train.h"
 #include "internal.h"
 
 using namespace gsk;
@@ -60,6 +61,8 @@ struct gs_plan {
       v_totals;
   // losses
   Buf l_coef, l_part;
+  // adaptive control and metrics
+  Buf d_action, d_count, d_offsets, d_scan_tmp, d_totals, m_sse, m_max, m_out, m_stack, m_loss;
   Buf skipped;  // unsigned long long [2]: projection, voxelization
   // host side
   gs_view *stage = nullptr;          // pinned staging of per-view constants
@@ -74,6 +77,8 @@ struct gs_plan {
   ProjArgs pargs{};
   VoxArgs vargs{};
   uint64_t p_entries = 0, v_entries = 0;
+  // method option: rectified (R^2-Gaussian) or unrectified (X-3DGS) projection
+  int rectify = 1;
   // per-stage timing
   bool timing = false;
   struct Timed {
@@ -288,7 +293,8 @@ bool same_proj(const gs_plan *pl, const gs_gaussians *g, const gs_view *views, i
                float cutoff) {
   const ProjKey &k = pl->pkey;
   if (!pl->p_valid || k.mean != g->mean || k.scale != g->scale || k.quat != g->quat ||
-      k.dens != g->density || k.n != g->n || k.cutoff != cutoff || (int32_t)k.views.size() != nv)
+      k.dens != g->density || k.n != g->n || k.cutoff != cutoff || (int32_t)k.views.size() != nv ||
+      pl->pargs.rectify != pl->rectify)
     return false;
   return std::memcmp(k.views.data(), views, sizeof(gs_view) * (size_t)nv) == 0;
 }
@@ -317,6 +323,7 @@ gs_status proj_bin(gs_plan *pl, const gs_gaussians *g, const gs_view *views, int
     return fail(GS_EUNSUPPORTED, "detector has more than 16384 tiles of 16x16 pixels");
   a.C = (int)((a.M + kChunk - 1) / kChunk);
   cutoff_consts(cutoff, a.kappa, a.thr, a.qmax);
+  a.rectify = pl->rectify;
   const int64_t VM = (int64_t)nv * a.M, VT = (int64_t)nv * a.T, VC = (int64_t)nv * a.C;
   if (VT + 1 > 0x7fffffffLL || VC + 1 > 0x7fffffffLL)
     return fail(GS_EUNSUPPORTED, "too many views in one call");
@@ -482,7 +489,9 @@ void gs_plan_destroy(gs_plan *p) {
                  &p->p_chunk_cnt, &p->p_chunk_start, &p->p_offsets, &p->p_list, &p->p_slots,
                  &p->p_totals, &p->p_part, &p->p_scan_tmp, &p->v_rec, &p->v_count, &p->v_offsets, &p->v_scan_tmp, &p->v_hist,
                  &p->v_tile_total, &p->v_tile_start, &p->v_list, &p->v_slots, &p->v_totals,
-                 &p->l_coef, &p->l_part, &p->skipped};
+                 &p->l_coef, &p->l_part, &p->skipped, &p->d_action, &p->d_count, &p->d_offsets,
+                 &p->d_scan_tmp, &p->d_totals, &p->m_sse, &p->m_max, &p->m_out, &p->m_stack,
+                 &p->m_loss};
   for (Buf *b : bufs) release(p, *b);
   if (p->stage) (void)hipHostFree(p->stage);
   if (p->readback) (void)hipHostFree(p->readback);
@@ -507,6 +516,33 @@ gs_status gs_plan_status(gs_plan *p, int64_t *skipped, int64_t *tile_entries) {
     return fail(GS_EHIP, "status readback failed");
   if (skipped) *skipped = (int64_t)(h[0] + h[1]);
   return GS_OK;
+}
+
+gs_status gs_plan_set_rectify(gs_plan *p, int32_t enable) {
+  if (!p) return fail(GS_EINVAL, "plan is NULL");
+  p->rectify = enable != 0;
+  return GS_OK;
+}
+
+gs_status gs_project_mean_mu(const gs_gaussians *g, const gs_view *views, int32_t n_views,
+                             float *mu_out, float *density_out, gs_plan *plan,
+                             hipStream_t stream) {
+  GS_TRY(check_gaussians(g));
+  GS_TRY(check_views(views, n_views));
+  if (!mu_out && !density_out) return fail(GS_EINVAL, "mu_out and density_out are both NULL");
+  if (!plan) return fail(GS_EINVAL, "plan is NULL");
+  plan->used = true;
+  plan->last_stream = stream;
+  if (g->n == 0) return GS_OK;
+  ProjArgs a{};
+  a.mean = g->mean; a.scale = g->scale; a.quat = g->quat; a.dens = g->density;
+  a.M = g->n;
+  a.V = n_views;
+  GS_TRY(upload_views(plan, views, n_views, stream));
+  a.views = P<DevView>(plan->p_views);
+  plan->p_valid = false;  // the view buffer now holds these views
+  launch_mean_mu(a, mu_out, density_out, stream);
+  return check_launch("mean rectification factor");
 }
 
 gs_status gs_plan_set_timing(gs_plan *p, int32_t enable) {
@@ -594,9 +630,9 @@ gs_status gs_project_fwd(const gs_gaussians *g, const gs_view *views, int32_t n_
   return GS_OK;
 }
 
-gs_status gs_project_bwd(const gs_gaussians *g, const gs_view *views, int32_t n_views, float cutoff,
-                         const float *grad_image, const gs_grads *grads, int32_t accumulate,
-                         gs_plan *plan, hipStream_t stream) {
+static gs_status project_bwd(const gs_gaussians *g, const gs_view *views, int32_t n_views, float cutoff,
+                      const float *grad_image, const gs_grads *grads, int32_t accumulate,
+                      const ChainStats &st, gs_plan *plan, hipStream_t stream) {
   GS_TRY(check_gaussians(g));
   GS_TRY(check_views(views, n_views));
   GS_TRY(check_cutoff(cutoff));
@@ -610,7 +646,7 @@ gs_status gs_project_bwd(const gs_gaussians *g, const gs_view *views, int32_t n_
     GS_TRY(proj_bin(plan, g, views, n_views, cutoff, stream));
   const ProjArgs &a = plan->pargs;
   GS_TRY(ensure(plan, plan->p_slots, 24 * (size_t)plan->p_entries, stream));
-  GS_TRY(ensure(plan, plan->p_part, 64 * (size_t)proj_chain_chunks(a.V) * (size_t)a.M, stream));
+  GS_TRY(ensure(plan, plan->p_part, 72 * (size_t)proj_chain_chunks(a.V) * (size_t)a.M, stream));
   {
     StageTimer t(plan, GS_STAGE_RENDER_BWD, stream);
     launch_render_bwd(a, P<Rec2>(plan->p_rec), P<uint2>(plan->p_list),
@@ -620,9 +656,27 @@ gs_status gs_project_bwd(const gs_gaussians *g, const gs_view *views, int32_t n_
     StageTimer t(plan, GS_STAGE_PROJ_CHAIN, stream);
     launch_proj_chain(a, P<Rec2>(plan->p_rec), P<uint32_t>(plan->p_offsets),
                       P<float>(plan->p_slots), P<float>(plan->p_part), grads->mean, grads->scale,
-                      grads->quat, grads->density, accumulate, stream);
+                      grads->quat, grads->density, accumulate, st, stream);
   }
   return check_launch("projection backward");
+}
+
+gs_status gs_project_bwd(const gs_gaussians *g, const gs_view *views, int32_t n_views, float cutoff,
+                         const float *grad_image, const gs_grads *grads, int32_t accumulate,
+                         gs_plan *plan, hipStream_t stream) {
+  return project_bwd(g, views, n_views, cutoff, grad_image, grads, accumulate,
+                     ChainStats{nullptr, nullptr, 0.f}, plan, stream);
+}
+
+gs_status gs_project_bwd_stats(const gs_gaussians *g, const gs_view *views, int32_t n_views,
+                               float cutoff, const float *grad_image, const gs_grads *grads,
+                               int32_t accumulate, const gs_grad_stats *stats, gs_plan *plan,
+                               hipStream_t stream) {
+  if (!stats || !stats->grad_sum || !stats->visible)
+    return fail(GS_EINVAL, "stats and its arrays must not be NULL");
+  if (!std::isfinite(stats->scale)) return fail(GS_EINVAL, "stats->scale not finite");
+  return project_bwd(g, views, n_views, cutoff, grad_image, grads, accumulate,
+                     ChainStats{stats->grad_sum, stats->visible, stats->scale}, plan, stream);
 }
 
 gs_status gs_voxelize_fwd(const gs_gaussians *g, const gs_grid *grid, float cutoff, float *volume,
@@ -725,6 +779,180 @@ gs_status gs_loss_tv(const float *volume, int32_t nx, int32_t ny, int32_t nz, fl
   launch_tv(volume, nx, ny, nz, weight, grad, accumulate, P<float>(plan->l_part), &n_part, stream);
   launch_tv_finish(P<float>(plan->l_part), n_part, loss_out, stream);
   return check_launch("total variation");
+}
+
+// ------------------------------------------------------ training loop --
+
+namespace {
+
+ParamPtrs param_ptrs(const gs_params *p) {
+  return ParamPtrs{p->mean,   p->log_scale, p->quat,      p->density_raw, p->scale,
+                   p->density, p->m_mean,   p->m_scale,   p->m_quat,      p->m_density,
+                   p->v_mean, p->v_scale,   p->v_quat,    p->v_density};
+}
+
+gs_status check_params(const gs_params *p, bool moments) {
+  if (!p) return fail(GS_EINVAL, "params is NULL");
+  if (!p->mean || !p->log_scale || !p->quat || !p->density_raw || !p->scale || !p->density)
+    return fail(GS_EINVAL, "a parameter array is NULL");
+  if (moments && (!p->m_mean || !p->m_scale || !p->m_quat || !p->m_density || !p->v_mean ||
+                  !p->v_scale || !p->v_quat || !p->v_density))
+    return fail(GS_EINVAL, "an Adam moment array is NULL");
+  return GS_OK;
+}
+
+double softplus_inv_d(double y) { return y > 30.0 ? y : std::log(std::expm1(y)); }
+
+}  // namespace
+
+gs_status gs_adam_step(const gs_params *p, int64_t n, const gs_grads *grads,
+                       const gs_adam_config *cfg, hipStream_t stream) {
+  GS_TRY(check_params(p, true));
+  if (!grads || !cfg) return fail(GS_EINVAL, "grads or cfg is NULL");
+  if (n < 0) return fail(GS_EINVAL, "n < 0");
+  if (cfg->step < 1) return fail(GS_EINVAL, "step must be >= 1");
+  if (n == 0) return GS_OK;
+  if (!grads->mean || !grads->scale || !grads->quat || !grads->density)
+    return fail(GS_EINVAL, "a gradient array is NULL");
+  const float lr[4] = {cfg->lr_mean, cfg->lr_scale, cfg->lr_quat, cfg->lr_density};
+  for (float l : lr)
+    if (!std::isfinite(l) || l < 0.f) return fail(GS_EINVAL, "learning rates must be finite and >= 0");
+  const double b1 = 0.9, b2 = 0.999;
+  AdamArgs a{};
+  a.raw[0] = p->mean; a.raw[1] = p->log_scale; a.raw[2] = p->quat; a.raw[3] = p->density_raw;
+  a.m[0] = p->m_mean; a.m[1] = p->m_scale; a.m[2] = p->m_quat; a.m[3] = p->m_density;
+  a.v[0] = p->v_mean; a.v[1] = p->v_scale; a.v[2] = p->v_quat; a.v[3] = p->v_density;
+  a.grad[0] = grads->mean; a.grad[1] = grads->scale; a.grad[2] = grads->quat;
+  a.grad[3] = grads->density;
+  a.scale = p->scale;
+  a.density = p->density;
+  a.n = n;
+  for (int k = 0; k < 4; ++k) a.lr[k] = lr[k];
+  a.beta1 = (float)b1;
+  a.beta2 = (float)b2;
+  a.omb1 = (float)(1.0 - b1);
+  a.omb2 = (float)(1.0 - b2);
+  a.eps = 1e-15f;
+  a.bc1_inv = (float)(1.0 / (1.0 - std::pow(b1, cfg->step)));
+  a.bc2_inv = (float)(1.0 / (1.0 - std::pow(b2, cfg->step)));
+  launch_adam(a, stream);
+  return check_launch("adam step");
+}
+
+gs_status gs_params_activate(const gs_params *p, int64_t n, hipStream_t stream) {
+  GS_TRY(check_params(p, false));
+  if (n < 0) return fail(GS_EINVAL, "n < 0");
+  if (n == 0) return GS_OK;
+  launch_activate(p->log_scale, p->density_raw, p->scale, p->density, n, 0, stream);
+  return check_launch("activate");
+}
+
+gs_status gs_params_from_activated(const gs_params *p, int64_t n, hipStream_t stream) {
+  GS_TRY(check_params(p, false));
+  if (n < 0) return fail(GS_EINVAL, "n < 0");
+  if (n == 0) return GS_OK;
+  launch_activate(p->log_scale, p->density_raw, p->scale, p->density, n, 1, stream);
+  return check_launch("inverse activation");
+}
+
+gs_status gs_densify(const gs_params *src, int64_t n, const gs_grad_stats *stats,
+                     const float *normals, const gs_densify_config *cfg, gs_params *dst,
+                     int64_t dst_capacity, int32_t *action, int64_t *n_out, gs_plan *plan,
+                     hipStream_t stream) {
+  GS_TRY(check_params(src, true));
+  GS_TRY(check_params(dst, true));
+  if (!stats || !stats->grad_sum || !stats->visible) return fail(GS_EINVAL, "stats is incomplete");
+  if (!cfg || !n_out || !plan) return fail(GS_EINVAL, "cfg, n_out or plan is NULL");
+  if (n < 0 || n > 0x3fffffffLL) return fail(GS_EINVAL, "n out of 0..2^30-1");
+  if (dst_capacity < 0) return fail(GS_EINVAL, "dst_capacity < 0");
+  if (cfg->densify && !normals) return fail(GS_EINVAL, "normals are needed when densifying");
+  if (!(cfg->min_density > 0.f) || !(cfg->clone_max_scale > 0.f) ||
+      !std::isfinite(cfg->grad_threshold) || !std::isfinite(cfg->min_density) ||
+      !std::isfinite(cfg->clone_max_scale))
+    return fail(GS_EINVAL, "min_density and clone_max_scale must be > 0, threshold finite");
+  plan->used = true;
+  plan->last_stream = stream;
+  *n_out = 0;
+  if (n == 0) return GS_OK;
+  GS_TRY(ensure(plan, plan->d_action, 4 * (size_t)n, stream));
+  GS_TRY(ensure(plan, plan->d_count, 4 * (size_t)n, stream));
+  GS_TRY(ensure(plan, plan->d_offsets, 4 * ((size_t)n + 1), stream));
+  GS_TRY(ensure(plan, plan->d_scan_tmp, 4 * (size_t)(2 * ((n + 4095) / 4096) + 1), stream));
+  GS_TRY(ensure(plan, plan->d_totals, 8, stream));
+  DensifyArgs a{};
+  a.src = param_ptrs(src);
+  a.dst = param_ptrs(dst);
+  a.n = n;
+  a.grad_sum = stats->grad_sum;
+  a.visible = stats->visible;
+  a.normals = normals;
+  a.grad_threshold = cfg->grad_threshold;
+  a.t_keep = (float)softplus_inv_d((double)cfg->min_density);
+  a.t_half = (float)softplus_inv_d(2.0 * (double)cfg->min_density);
+  a.t_scale = (float)std::log((double)cfg->clone_max_scale);
+  a.log_split = (float)std::log(1.6);
+  a.densify = cfg->densify != 0;
+  int32_t *act = action ? action : P<int32_t>(plan->d_action);
+  launch_densify_count(a, act, P<uint32_t>(plan->d_count), stream);
+  launch_scan_big(P<uint32_t>(plan->d_count), P<uint32_t>(plan->d_offsets), n,
+                  P<uint32_t>(plan->d_scan_tmp), P<unsigned long long>(plan->d_totals), stream);
+  GS_TRY(check_launch("densify count"));
+  if (hipMemcpyAsync(plan->readback, plan->d_totals.p, 8, hipMemcpyDeviceToHost, stream) != hipSuccess)
+    return fail(GS_EHIP, "densify readback");
+  GS_TRY(sync_stream(plan, stream));
+  const int64_t total = (int64_t)plan->readback[0];
+  *n_out = total;
+  if (total > dst_capacity)
+    return fail(GS_EOVERFLOW, "densify needs " + std::to_string(total) + " Gaussians, dst holds " +
+                                  std::to_string(dst_capacity));
+  launch_densify_write(a, act, P<uint32_t>(plan->d_offsets), stream);
+  GS_TRY(check_launch("densify write"));
+  return sync_stream(plan, stream);
+}
+
+gs_status gs_volume_metrics(const float *volume, const float *gt, int32_t nx, int32_t ny, int32_t nz,
+                            double *psnr, double *ssim, gs_plan *plan, hipStream_t stream) {
+  if (!volume || !gt || !plan) return fail(GS_EINVAL, "volume, gt or plan is NULL");
+  if (nx < 1 || ny < 1 || nz < 1) return fail(GS_EINVAL, "sizes must be >= 1");
+  plan->used = true;
+  plan->last_stream = stream;
+  const int64_t N = (int64_t)nx * ny * nz;
+  const int nb = metric_num_blocks(N);
+  GS_TRY(ensure(plan, plan->m_sse, 8 * (size_t)nb, stream));
+  GS_TRY(ensure(plan, plan->m_max, 4 * (size_t)nb, stream));
+  GS_TRY(ensure(plan, plan->m_out, 16, stream));
+  GS_TRY(ensure(plan, plan->m_loss, 4 * 9, stream));
+  launch_metric_sums(volume, gt, N, P<double>(plan->m_sse), P<float>(plan->m_max),
+                     P<double>(plan->m_out), stream);
+  if (ssim) {
+    GS_TRY(ensure(plan, plan->m_stack, 2 * 4 * (size_t)N, stream));
+    GS_TRY(ensure(plan, plan->l_coef, 3 * 4 * (size_t)N, stream));
+    float *xs = P<float>(plan->m_stack), *ys = xs + N;
+    // (slices, rows, columns) of the stacks normal to x, y, z
+    const int dims[3][3] = {{nx, nz, ny}, {ny, nz, nx}, {nz, ny, nx}};
+    for (int axis = 0; axis < 3; ++axis) {
+      const int n = dims[axis][0], h = dims[axis][1], w = dims[axis][2];
+      const int nbs = ssim_num_blocks(n, h, w);
+      GS_TRY(ensure(plan, plan->l_part, 2 * sizeof(float) * (size_t)nbs, stream));
+      launch_slices(volume, nx, ny, nz, axis, P<double>(plan->m_out), xs, stream);
+      launch_slices(gt, nx, ny, nz, axis, P<double>(plan->m_out), ys, stream);
+      launch_ssim_coeffs(xs, ys, n, h, w, P<float>(plan->l_coef), P<float>(plan->l_part), stream);
+      launch_loss_finish(P<float>(plan->l_part), nbs, n, h, w, 0.f, P<float>(plan->m_loss) + 3 * axis,
+                         stream);
+    }
+  }
+  GS_TRY(check_launch("volume metrics"));
+  double host_out[2];
+  float host_loss[9];
+  if (hipMemcpyAsync(host_out, plan->m_out.p, 16, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      (ssim && hipMemcpyAsync(host_loss, plan->m_loss.p, 36, hipMemcpyDeviceToHost, stream) !=
+                   hipSuccess))
+    return fail(GS_EHIP, "metrics readback");
+  GS_TRY(sync_stream(plan, stream));
+  if (!(host_out[1] > 0.0)) return fail(GS_EINVAL, "max(gt) must be > 0");
+  if (psnr) *psnr = 10.0 * std::log10(host_out[1] * host_out[1] / (host_out[0] / (double)N));
+  if (ssim) *ssim = ((double)host_loss[2] + (double)host_loss[5] + (double)host_loss[8]) / 3.0;
+  return GS_OK;
 }
 
 }  // extern "C"

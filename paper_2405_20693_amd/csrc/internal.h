@@ -260,8 +260,10 @@ struct ProjArgs {
   int width, height, TX, TY, T;   // tiles per view T = TX * TY
   int C;                          // chunks per view
   float kappa, thr, qmax;         // cutoff, exp2-threshold (-qmax), positive-form limit
+  int rectify;                    // 1: rho_hat = mu rho (Eq. 7); 0: rho_hat = rho (unrectified)
 };
 
+void launch_mean_mu(const ProjArgs &a, float *mu_out, float *density_out, hipStream_t s);
 void launch_proj_hist(const ProjArgs &a, Rec2 *rec, uint32_t *hist, uint32_t *chunk_cnt,
                       unsigned long long *skipped, hipStream_t s);
 void launch_hist_colscan(int groups, int C, int T, uint32_t *hist, uint32_t *tile_total,
@@ -277,10 +279,20 @@ void launch_render_fwd(const ProjArgs &a, const Rec2 *rec, const uint2 *list,
 void launch_render_bwd(const ProjArgs &a, const Rec2 *rec, const uint2 *list,
                        const uint32_t *tile_start, const float *grad_image, float *slots,
                        hipStream_t s);
-int proj_chain_chunks(int n_views);  // partial-gradient chunks (16 floats per Gaussian each)
+int proj_chain_chunks(int n_views);  // partial-gradient chunks (16 or 18 floats per Gaussian each)
+// Optional densification statistics of the projection backward: per Gaussian,
+// ndc_sum += scale * sum over visible views of |dL/dp_hat| in normalised
+// device coordinates, visible += number of those views (no statistics when
+// ndc_sum is null).
+struct ChainStats {
+  float *ndc_sum;
+  int32_t *visible;
+  float scale;
+};
 void launch_proj_chain(const ProjArgs &a, const Rec2 *rec, const uint32_t *offsets,
                        const float *slots, float *part, float *g_mean, float *g_scale,
-                       float *g_quat, float *g_dens, int accumulate, hipStream_t s);
+                       float *g_quat, float *g_dens, int accumulate, const ChainStats &st,
+                       hipStream_t s);
 
 struct VoxArgs {
   const float *mean, *scale, *quat, *dens;
@@ -322,5 +334,47 @@ void launch_tv(const float *vol, int nx, int ny, int nz, float weight, float *gr
                float *partials, int *n_part, hipStream_t s);
 void launch_tv_finish(const float *partials, int n_part, float *loss_out, hipStream_t s);
 int tv_num_blocks(int nx, int ny, int nz);
+
+// ------------------------------------------------------ training loop --
+
+struct AdamArgs {
+  float *raw[4];         // mean, log_scale, quat, density_raw
+  float *m[4], *v[4];
+  const float *grad[4];  // with respect to the activated parameters
+  float *scale, *density;
+  int64_t n;
+  float lr[4];
+  float beta1, beta2, omb1, omb2;  // beta and 1 - beta, each rounded once from double
+  float eps, bc1_inv, bc2_inv;
+};
+void launch_adam(const AdamArgs &a, hipStream_t s);
+void launch_activate(float *log_scale, float *density_raw, float *scale, float *density, int64_t n,
+                     int inverse, hipStream_t s);
+
+struct ParamPtrs {
+  float *mean, *log_scale, *quat, *density_raw, *scale, *density;
+  float *m_mean, *m_scale, *m_quat, *m_density, *v_mean, *v_scale, *v_quat, *v_density;
+};
+struct DensifyArgs {
+  ParamPtrs src, dst;
+  int64_t n;
+  const float *grad_sum;
+  const int32_t *visible;
+  const float *normals;
+  float grad_threshold;
+  float t_keep, t_half, t_scale;  // raw-space thresholds
+  float log_split;                // log(1.6)
+  int densify;
+};
+void launch_densify_count(const DensifyArgs &a, int32_t *action, uint32_t *count, hipStream_t s);
+void launch_densify_write(const DensifyArgs &a, const int32_t *action, const uint32_t *offset,
+                          hipStream_t s);
+
+int metric_num_blocks(int64_t n);
+// out[0] = sum of squared differences, out[1] = max(gt)
+void launch_metric_sums(const float *vol, const float *gt, int64_t n, double *part_sse,
+                        float *part_max, double *out, hipStream_t s);
+void launch_slices(const float *vol, int nx, int ny, int nz, int axis, const double *range,
+                   float *out, hipStream_t s);
 
 }  // namespace gsk

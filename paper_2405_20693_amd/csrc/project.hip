@@ -59,7 +59,7 @@ __device__ inline Rec2 make_rec2(const Gauss &G, const Proj2 &P, const DevView &
   r.c00 = -0.5f * kLog2e * P.A00 * V.hu * V.hu;
   r.c01 = -kLog2e * P.A01 * V.hu * V.hv;
   r.c11 = -0.5f * kLog2e * P.A11 * V.hv * V.hv;
-  r.rho = P.mu * G.rho;
+  r.rho = (a.rectify ? P.mu : 1.f) * G.rho;
   float ru = a.kappa * sqrtf(P.S00) * V.inv_hu;
   float rv = a.kappa * sqrtf(P.S11) * V.inv_hv;
   const float eps = 1e-3f;
@@ -115,6 +115,35 @@ __global__ __launch_bounds__(kBlock) void k_proj_hist(ProjArgs a, Rec2 *__restri
     chunk_cnt[v * a.C + c] = tot;
     if (sk) atomicAdd(skipped, (unsigned long long)sk);
   }
+}
+
+// Mean over the views of each Gaussian's rectification factor mu (views where
+// the Gaussian is culled are left out; 0 if culled in every view), and
+// optionally rho / mean(mu).
+__global__ __launch_bounds__(kBlock) void k_mean_mu(ProjArgs a, float *__restrict__ mu_out,
+                                                    float *__restrict__ density_out) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= a.M) return;
+  Gauss G;
+  load_gauss(a.mean, a.scale, a.quat, a.dens, g, G);
+  float sum = 0.f;
+  int n = 0;
+  for (int v = 0; v < a.V; ++v) {
+    Proj2 P;
+    project_one(G, a.views[v], P);
+    if (P.ok) {
+      sum += P.mu;
+      ++n;
+    }
+  }
+  const float m = n ? sum / (float)n : 0.f;
+  if (mu_out) mu_out[g] = m;
+  if (density_out) density_out[g] = m > 0.f ? G.rho / m : 0.f;
+}
+
+void launch_mean_mu(const ProjArgs &a, float *mu_out, float *density_out, hipStream_t s) {
+  unsigned nb = (unsigned)((a.M + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_mean_mu, dim3(nb), dim3(kBlock), 0, s, a, mu_out, density_out);
 }
 
 void launch_proj_hist(const ProjArgs &a, Rec2 *rec, uint32_t *hist, uint32_t *chunk_cnt,
@@ -451,15 +480,17 @@ void launch_render_bwd(const ProjArgs &a, const Rec2 *rec, const uint2 *list,
 // gradients with respect to p, s, R and rho (16 values, component-major);
 // k_proj_chain_reduce sums the chunks in order and finishes the quaternion.
 constexpr int kChainViews = 8;
-constexpr int kChainParts = 16;
+constexpr int kChainParts = 16;  // gradient parts; +2 with statistics (NDC norm sum, views)
 
 __global__ __launch_bounds__(kBlock) void k_proj_chain(ProjArgs a, const Rec2 *__restrict__ rec,
                                                        const uint32_t *__restrict__ offsets,
                                                        const float *__restrict__ slots,
-                                                       float *__restrict__ part) {
+                                                       float *__restrict__ part, int stats) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (g >= a.M) return;
   const int vc = blockIdx.y;
+  const int n_parts = kChainParts + (stats ? 2 : 0);
+  float ndc_sum = 0.f, n_vis = 0.f;
   Gauss G;
   load_gauss(a.mean, a.scale, a.quat, a.dens, g, G);
   float gp[3] = {0.f, 0.f, 0.f}, gs[3] = {0.f, 0.f, 0.f}, gR[9] = {0.f};
@@ -480,13 +511,19 @@ __global__ __launch_bounds__(kBlock) void k_proj_chain(ProjArgs a, const Rec2 *_
       const DevView V = a.views[v];
       Proj2 P;
       project_one(G, V, P);
-      const float rh = P.mu * G.rho;
+      const float mu = a.rectify ? P.mu : 1.f;
+      const float rh = mu * G.rho;
       // world-unit moments
       const float T1 = S[1] * V.hu, T2 = S[2] * V.hv;
       const float T3 = S[3] * V.hu * V.hu, T4 = S[4] * V.hu * V.hv, T5 = S[5] * V.hv * V.hv;
       const float g_rh = S[0];
       const float gph0 = rh * (P.A00 * T1 + P.A01 * T2);
       const float gph1 = rh * (P.A01 * T1 + P.A11 * T2);
+      if (stats) {  // |dL/dp_hat| in normalised device coordinates (half-width = 1)
+        const float nu = gph0 * V.hu * (0.5f * a.width), nv = gph1 * V.hv * (0.5f * a.height);
+        ndc_sum += sqrtf(nu * nu + nv * nv);
+        n_vis += 1.f;
+      }
       // dL/dA as a symmetric matrix (each entry), then dL/dSigma_hat = -A Gb A
       const float Gb00 = -0.5f * rh * T3, Gb01 = -0.5f * rh * T4, Gb11 = -0.5f * rh * T5;
       const float X00 = P.A00 * Gb00 + P.A01 * Gb01, X01 = P.A00 * Gb01 + P.A01 * Gb11;
@@ -513,8 +550,9 @@ __global__ __launch_bounds__(kBlock) void k_proj_chain(ProjArgs a, const Rec2 *_
           gs[j] += gM * G.R[3 * i + j];
         }
       // rho_hat = mu rho,  mu = sqrt(2 pi / m),  m = sum_j (r_j / s_j)^2,  r = R^T d
-      grho += P.mu * g_rh;
-      const float gmu = G.rho * g_rh;
+      grho += mu * g_rh;
+      // the rectification factor's own dependence on p, s, q (none when unrectified)
+      const float gmu = a.rectify ? G.rho * g_rh : 0.f;
       const float gm = gmu * (-0.5f * P.mu / P.m);
       float gd[3] = {0.f, 0.f, 0.f};
       for (int j = 0; j < 3; ++j) {
@@ -558,25 +596,39 @@ __global__ __launch_bounds__(kBlock) void k_proj_chain(ProjArgs a, const Rec2 *_
       for (int i = 0; i < 3; ++i) gp[i] += W[i] * gt[0] + W[3 + i] * gt[1] + W[6 + i] * gt[2];
     }
   }
-  float *o = part + (int64_t)vc * kChainParts * a.M + g;
+  float *o = part + (int64_t)vc * n_parts * a.M + g;
   for (int i = 0; i < 3; ++i) o[(int64_t)i * a.M] = gp[i];
   for (int i = 0; i < 3; ++i) o[(int64_t)(3 + i) * a.M] = gs[i];
   for (int i = 0; i < 9; ++i) o[(int64_t)(6 + i) * a.M] = gR[i];
   o[(int64_t)15 * a.M] = grho;
+  if (stats) {
+    o[(int64_t)16 * a.M] = ndc_sum;
+    o[(int64_t)17 * a.M] = n_vis;
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_proj_chain_reduce(ProjArgs a, int n_chunks,
                                                               const float *__restrict__ part,
                                                               float *g_mean, float *g_scale,
                                                               float *g_quat, float *g_dens,
-                                                              int accumulate) {
+                                                              int accumulate, ChainStats st) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (g >= a.M) return;
-  float sum[kChainParts];
-  for (int k = 0; k < kChainParts; ++k) sum[k] = 0.f;
+  const int stats = st.ndc_sum != nullptr;
+  const int n_parts = kChainParts + (stats ? 2 : 0);
+  float sum[kChainParts + 2];
+  for (int k = 0; k < kChainParts + 2; ++k) sum[k] = 0.f;
   for (int c = 0; c < n_chunks; ++c) {
-    const float *o = part + (int64_t)c * kChainParts * a.M + g;
+    const float *o = part + (int64_t)c * n_parts * a.M + g;
     for (int k = 0; k < kChainParts; ++k) sum[k] += o[(int64_t)k * a.M];
+    if (stats) {
+      sum[16] += o[(int64_t)16 * a.M];
+      sum[17] += o[(int64_t)17 * a.M];
+    }
+  }
+  if (stats) {
+    st.ndc_sum[g] += st.scale * sum[16];
+    st.visible[g] += (int)sum[17];
   }
   Gauss G;
   load_gauss(a.mean, a.scale, a.quat, a.dens, g, G);
@@ -596,12 +648,15 @@ int proj_chain_chunks(int n_views) { return (n_views + kChainViews - 1) / kChain
 
 void launch_proj_chain(const ProjArgs &a, const Rec2 *rec, const uint32_t *offsets,
                        const float *slots, float *part, float *g_mean, float *g_scale,
-                       float *g_quat, float *g_dens, int accumulate, hipStream_t s) {
+                       float *g_quat, float *g_dens, int accumulate, const ChainStats &st,
+                       hipStream_t s) {
   unsigned nb = (unsigned)((a.M + kBlock - 1) / kBlock);
   const int nc = proj_chain_chunks(a.V);
-  hipLaunchKernelGGL(k_proj_chain, dim3(nb, nc), dim3(kBlock), 0, s, a, rec, offsets, slots, part);
+  const int stats = st.ndc_sum != nullptr;
+  hipLaunchKernelGGL(k_proj_chain, dim3(nb, nc), dim3(kBlock), 0, s, a, rec, offsets, slots, part,
+                     stats);
   hipLaunchKernelGGL(k_proj_chain_reduce, dim3(nb), dim3(kBlock), 0, s, a, nc, part, g_mean,
-                     g_scale, g_quat, g_dens, accumulate);
+                     g_scale, g_quat, g_dens, accumulate, st);
 }
 
 }  // namespace gsk

@@ -50,6 +50,10 @@ class Plan:
         N.call("gs_plan_status", self._h, ctypes.byref(sk), ctypes.byref(en))
         return {"skipped": sk.value, "tile_entries": en.value}
 
+    def set_rectify(self, enable=True):
+        """False: unrectified (3DGS-style) projection rho_hat = rho."""
+        N.call("gs_plan_set_rectify", self._h, int(bool(enable)))
+
     def set_timing(self, enable=True):
         N.call("gs_plan_set_timing", self._h, int(bool(enable)))
 
@@ -176,6 +180,18 @@ def project_backward(mean, scale, quat, density, views: Views, grad_image, plan,
            _dev(grad_image, "grad_image", (views.n, views.height, views.width)), ctypes.byref(gr),
            int(bool(accumulate)), plan.handle, _stream())
     return grads
+
+
+def mean_mu(mean, scale, quat, density, views: Views, plan=None):
+    """Per-Gaussian mean rectification factor over the views, and the density
+    divided by it (what the unrectified X-3DGS variant voxelizes)."""
+    g = _gaussians(mean, scale, quat, density)
+    mu = torch.empty_like(density)
+    dens = torch.empty_like(density)
+    plan = plan or Plan()  # held until the call returns (its __del__ frees the plan)
+    N.call("gs_project_mean_mu", ctypes.byref(g), views.arr, views.n, _dev(mu, "mu_out"),
+           _dev(dens, "density_out"), plan.handle, _stream())
+    return mu, dens
 
 
 def voxelize_forward(mean, scale, quat, density, grid, cutoff=3.0, plan=None, out=None):

@@ -103,3 +103,19 @@ def test_product_path_does_not_use_the_oracle():
         if f.endswith((".py", ".c")):
             txt = open(os.path.join(ROOT, "oracle", f)).read()
             assert "paper_2405_20693_amd" not in txt.replace("``paper_2405_20693_amd``", ""), f
+
+
+def test_bindings_keep_temporary_plans_alive():
+    """A temporary Plan must be bound to a name for the whole call: reading
+    .handle off an unnamed `plan or Plan()` lets the Plan be collected (and
+    its workspace freed) before the library uses it."""
+    import ast
+    pkg = os.path.join(ROOT, "paper_2405_20693_amd")
+    for name in sorted(os.listdir(pkg)):
+        if not name.endswith(".py"):
+            continue
+        tree = ast.parse(open(os.path.join(pkg, name)).read())
+        for node in ast.walk(tree):
+            if isinstance(node, ast.Attribute) and node.attr == "handle":
+                inner = node.value
+                assert not isinstance(inner, (ast.BoolOp, ast.Call)), f"{name}:{node.lineno}"

@@ -375,6 +375,18 @@ def _cone_rays(theta, scan: ConeScan, rows):
     return src, d
 
 
+def phantom_volume(wl: Workload, grid: Grid):
+    """Ground-truth density f of the workload's phantom at the voxel centres
+    of grid, [nz][ny][nx] FP32 (the volume its measured projections
+    integrate)."""
+    ells = wl.extra["ellipsoids"]
+    ax = [grid.origin[k] + (np.arange(n) + 0.5) * grid.spacing[k]
+          for k, n in enumerate((grid.nx, grid.ny, grid.nz))]
+    z, y, x = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    pts = np.stack([x.ravel(), y.ravel(), z.ravel()], 1)
+    return _f32(phantom_value(ells, pts, clip=True).reshape(grid.nz, grid.ny, grid.nx))
+
+
 def measured_projections(wl: Workload, rows_per_chunk=64):
     scan = wl.scan
     ells = wl.extra["ellipsoids"]
