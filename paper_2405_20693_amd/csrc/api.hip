@@ -1,5 +1,6 @@
 // C ABI of the HIP path: argument validation, plan workspace and the launch
 // sequences of the projection, voxelization and loss entry points.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -55,7 +56,7 @@ struct gs_plan {
   bool used = false;
   // projection
   Buf p_views, p_rec, p_hist, p_tile_total, p_tile_start, p_chunk_cnt, p_chunk_start, p_offsets,
-      p_list, p_slots, p_totals, p_part, p_scan_tmp;
+      p_list, p_slots, p_totals, p_part, p_scan_tmp, p_fpart;
   // voxelization
   Buf v_rec, v_count, v_offsets, v_scan_tmp, v_hist, v_tile_total, v_tile_start, v_list, v_slots,
       v_totals;
@@ -321,7 +322,17 @@ gs_status proj_bin(gs_plan *pl, const gs_gaussians *g, const gs_view *views, int
   a.T = a.TX * a.TY;
   if (a.T > kMaxTilesPerGroup)
     return fail(GS_EUNSUPPORTED, "detector has more than 16384 tiles of 16x16 pixels");
-  a.C = (int)((a.M + kChunk - 1) / kChunk);
+  // binning chunks: 4096 Gaussians, halved while fewer than 512 (view, chunk)
+  // workgroups would run (few views); render: parts per tile list so that
+  // about 8192 workgroups run (one part when there are that many tiles)
+  a.cpt = kChunkPerThread;
+  while (a.cpt > 1 && (int64_t)nv * ((a.M + (int64_t)kBlock * a.cpt - 1) / ((int64_t)kBlock * a.cpt)) < 512)
+    a.cpt /= 2;
+  a.C = (int)((a.M + (int64_t)kBlock * a.cpt - 1) / ((int64_t)kBlock * a.cpt));
+  {
+    const int64_t tiles = (int64_t)nv * a.T;
+    a.parts = tiles >= 8192 ? 1 : (int)std::min<int64_t>(16, (8192 + tiles - 1) / tiles);
+  }
   cutoff_consts(cutoff, a.kappa, a.thr, a.qmax);
   a.rectify = pl->rectify;
   const int64_t VM = (int64_t)nv * a.M, VT = (int64_t)nv * a.T, VC = (int64_t)nv * a.C;
@@ -487,7 +498,7 @@ void gs_plan_destroy(gs_plan *p) {
   if (p->used) (void)hipDeviceSynchronize();
   Buf *bufs[] = {&p->p_views, &p->p_rec, &p->p_hist, &p->p_tile_total, &p->p_tile_start,
                  &p->p_chunk_cnt, &p->p_chunk_start, &p->p_offsets, &p->p_list, &p->p_slots,
-                 &p->p_totals, &p->p_part, &p->p_scan_tmp, &p->v_rec, &p->v_count, &p->v_offsets, &p->v_scan_tmp, &p->v_hist,
+                 &p->p_totals, &p->p_part, &p->p_scan_tmp, &p->p_fpart, &p->v_rec, &p->v_count, &p->v_offsets, &p->v_scan_tmp, &p->v_hist,
                  &p->v_tile_total, &p->v_tile_start, &p->v_list, &p->v_slots, &p->v_totals,
                  &p->l_coef, &p->l_part, &p->skipped, &p->d_action, &p->d_count, &p->d_offsets,
                  &p->d_scan_tmp, &p->d_totals, &p->m_sse, &p->m_max, &p->m_out, &p->m_stack,
@@ -622,8 +633,15 @@ gs_status gs_project_fwd(const gs_gaussians *g, const gs_view *views, int32_t n_
   GS_TRY(proj_bin(plan, g, views, n_views, cutoff, stream));
   {
     StageTimer t(plan, GS_STAGE_RENDER_FWD, stream);
+    float *partial = nullptr;
+    if (plan->pargs.parts > 1) {
+      GS_TRY(ensure(plan, plan->p_fpart,
+                    4 * (size_t)plan->pargs.parts * (size_t)plan->pargs.V * plan->pargs.T * kBlock,
+                    stream));
+      partial = P<float>(plan->p_fpart);
+    }
     launch_render_fwd(plan->pargs, P<Rec2>(plan->p_rec), P<uint2>(plan->p_list),
-                      P<uint32_t>(plan->p_tile_start), image, stream);
+                      P<uint32_t>(plan->p_tile_start), image, partial, stream);
   }
   GS_TRY(check_launch("render forward"));
   if (tp.owned) GS_TRY(sync_stream(plan, stream));

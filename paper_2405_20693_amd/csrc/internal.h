@@ -250,6 +250,22 @@ __device__ inline int xcd_remap(int b, int n) {
   return start + r;
 }
 
+// Part `part` of `parts` of the tile-list range [b, e), split on multiples of
+// 64 entries (one wave's batch) so that the parts of a long list get equal work.
+__device__ inline void list_part(uint32_t b, uint32_t e, int part, int parts, uint32_t &pb,
+                                 uint32_t &pe) {
+  if (parts == 1) {
+    pb = b;
+    pe = e;
+    return;
+  }
+  const uint32_t nb = (e - b + 63) / 64;
+  const uint32_t b0 = (uint32_t)(((uint64_t)nb * part) / parts);
+  const uint32_t b1 = (uint32_t)(((uint64_t)nb * (part + 1)) / parts);
+  pb = min(e, b + 64 * b0);
+  pe = min(e, b + 64 * b1);
+}
+
 // ------------------------------------------------------------ launchers --
 
 struct ProjArgs {
@@ -261,6 +277,8 @@ struct ProjArgs {
   int C;                          // chunks per view
   float kappa, thr, qmax;         // cutoff, exp2-threshold (-qmax), positive-form limit
   int rectify;                    // 1: rho_hat = mu rho (Eq. 7); 0: rho_hat = rho (unrectified)
+  int cpt;                        // Gaussians per thread per binning chunk (chunk = kBlock * cpt)
+  int parts;                      // workgroups per tile list in the render kernels (>= 1)
 };
 
 void launch_mean_mu(const ProjArgs &a, float *mu_out, float *density_out, hipStream_t s);
@@ -274,8 +292,10 @@ void launch_scan2(const uint32_t *in0, uint32_t *out0, int n0, const uint32_t *i
 void launch_proj_scatter(const ProjArgs &a, const Rec2 *rec, const uint32_t *hist,
                          const uint32_t *tile_start, const uint32_t *chunk_start, uint2 *list,
                          uint32_t *offsets, hipStream_t s);
+// With a.parts > 1, each part of a tile list writes its pixel sums to
+// partial [parts][V * T][256] and a second kernel adds the parts in order.
 void launch_render_fwd(const ProjArgs &a, const Rec2 *rec, const uint2 *list,
-                       const uint32_t *tile_start, float *image, hipStream_t s);
+                       const uint32_t *tile_start, float *image, float *partial, hipStream_t s);
 void launch_render_bwd(const ProjArgs &a, const Rec2 *rec, const uint2 *list,
                        const uint32_t *tile_start, const float *grad_image, float *slots,
                        hipStream_t s);

@@ -89,8 +89,8 @@ __global__ __launch_bounds__(kBlock) void k_proj_hist(ProjArgs a, Rec2 *__restri
   __syncthreads();
   const DevView V = a.views[v];
   uint32_t cnt = 0, skip = 0;
-  const int64_t g0 = (int64_t)c * kChunk;
-  for (int k = 0; k < kChunkPerThread; ++k) {
+  const int64_t g0 = (int64_t)c * kBlock * a.cpt;
+  for (int k = 0; k < a.cpt; ++k) {
     int64_t g = g0 + (int64_t)k * kBlock + tid;
     if (g >= a.M) break;
     Gauss G;
@@ -161,10 +161,23 @@ __global__ __launch_bounds__(kBlock) void k_hist_colscan(int groups, int C, int 
   if (id >= (int64_t)groups * T) return;
   int grp = (int)(id / T), t = (int)(id - (int64_t)grp * T);
   uint32_t run = 0;
-  for (int c = 0; c < C; ++c) {
-    int64_t idx = ((int64_t)grp * C + c) * T + t;
-    uint32_t x = hist[idx];
-    hist[idx] = run;
+  uint32_t *h = hist + (int64_t)grp * C * T + t;
+  // batches of 8 independent loads, then the prefix (long chunk columns when
+  // one view is binned in many small chunks)
+  int c = 0;
+  for (; c + 8 <= C; c += 8) {
+    uint32_t x[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = h[(int64_t)(c + k) * T];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      h[(int64_t)(c + k) * T] = run;
+      run += x[k];
+    }
+  }
+  for (; c < C; ++c) {
+    const uint32_t x = h[(int64_t)c * T];
+    h[(int64_t)c * T] = run;
     run += x;
   }
   tile_total[id] = run;
@@ -193,8 +206,8 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
   for (int t = tid; t < a.T; t += kBlock) cur[t] = ts[t] + h[t];
   __syncthreads();
   uint32_t base = chunk_start[v * a.C + c];
-  const int64_t g0 = (int64_t)c * kChunk;
-  for (int k = 0; k < kChunkPerThread; ++k) {
+  const int64_t g0 = (int64_t)c * kBlock * a.cpt;
+  for (int k = 0; k < a.cpt; ++k) {
     int64_t gk = g0 + (int64_t)k * kBlock;
     if (gk >= a.M) break;
     int64_t g = gk + tid;
@@ -241,10 +254,12 @@ void launch_proj_scatter(const ProjArgs &a, const Rec2 *rec, const uint32_t *his
 __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *__restrict__ rec,
                                                        const uint2 *__restrict__ list,
                                                        const uint32_t *__restrict__ tile_start,
-                                                       float *__restrict__ image) {
+                                                       float *__restrict__ image,
+                                                       float *__restrict__ partial) {
   __shared__ float4 s_r0[kBlock], s_r1[kBlock];
   __shared__ float4 s_k0[4][64], s_k1[4][64];
-  const int item = xcd_remap(blockIdx.x, gridDim.x);
+  const int wi = xcd_remap(blockIdx.x, gridDim.x);
+  const int item = wi / a.parts, part = wi - item * a.parts;
   const int v = item / a.T, t = item - v * a.T;
   const int ty = t / a.TX, tx = t - ty * a.TX;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -254,7 +269,8 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
   const float lx = (float)(lane & 7) - 0.5f * (kSub - 1), ly = (float)(lane >> 3) - 0.5f * (kSub - 1);
   const float lxx = lx * lx, lxy = lx * ly, lyy = ly * ly;
   const float hs = 0.5f * (kSub - 1);
-  const uint32_t beg = tile_start[item], end = tile_start[item + 1];
+  uint32_t beg, end;
+  list_part(tile_start[item], tile_start[item + 1], part, a.parts, beg, end);
   const Rec2 *rv = rec + (int64_t)v * a.M;
   const float thr = a.thr;
   float acc0 = 0.f, acc1 = 0.f;
@@ -322,14 +338,34 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
       __builtin_amdgcn_wave_barrier();  // the next chunk overwrites this wave's coefficients
     }
   }
-  if (px < a.width && py < a.height)
+  if (a.parts > 1)
+    partial[((int64_t)part * a.V * a.T + item) * kBlock + tid] = acc0 + acc1;
+  else if (px < a.width && py < a.height)
     image[((int64_t)v * a.height + py) * a.width + px] = acc0 + acc1;
 }
 
+// Sum of the parts of each tile's pixels, in part order.
+__global__ __launch_bounds__(kBlock) void k_render_parts(ProjArgs a, const float *__restrict__ partial,
+                                                         float *__restrict__ image) {
+  const int item = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int v = item / a.T, t = item - v * a.T;
+  const int ty = t / a.TX, tx = t - ty * a.TX;
+  const int px = tx * kTile + (w & 1) * kSub + (lane & 7);
+  const int py = ty * kTile + (w >> 1) * kSub + (lane >> 3);
+  const int64_t stride = (int64_t)a.V * a.T * kBlock;
+  const float *p = partial + (int64_t)item * kBlock + tid;
+  float acc = 0.f;
+  for (int k = 0; k < a.parts; ++k) acc += p[k * stride];
+  if (px < a.width && py < a.height) image[((int64_t)v * a.height + py) * a.width + px] = acc;
+}
+
 void launch_render_fwd(const ProjArgs &a, const Rec2 *rec, const uint2 *list,
-                       const uint32_t *tile_start, float *image, hipStream_t s) {
-  int n = a.V * a.T;
-  hipLaunchKernelGGL(k_render_fwd, dim3(n), dim3(kBlock), 0, s, a, rec, list, tile_start, image);
+                       const uint32_t *tile_start, float *image, float *partial, hipStream_t s) {
+  const int n = a.V * a.T * a.parts;
+  hipLaunchKernelGGL(k_render_fwd, dim3(n), dim3(kBlock), 0, s, a, rec, list, tile_start, image,
+                     partial);
+  if (a.parts > 1)
+    hipLaunchKernelGGL(k_render_parts, dim3(a.V * a.T), dim3(kBlock), 0, s, a, partial, image);
 }
 
 // ------------------------------------------------------ render backward --
@@ -353,7 +389,8 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *_
   __shared__ __align__(16) float s_G[kTile * kTile];
   __shared__ float s_acc[4][6][kBlock];
   __shared__ uint16_t s_q[4][kBlock];
-  const int item = xcd_remap(blockIdx.x, gridDim.x);
+  const int wi = xcd_remap(blockIdx.x, gridDim.x);
+  const int item = wi / a.parts, part = wi - item * a.parts;
   const int v = item / a.T, t = item - v * a.T;
   const int ty = t / a.TX, tx = t - ty * a.TX;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -368,7 +405,8 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *_
                    ? grad_image[((int64_t)v * a.height + gy) * a.width + gx]
                    : 0.f;
   }
-  const uint32_t beg = tile_start[item], end = tile_start[item + 1];
+  uint32_t beg, end;
+  list_part(tile_start[item], tile_start[item + 1], part, a.parts, beg, end);
   const Rec2 *rv = rec + (int64_t)v * a.M;
   for (uint32_t base = beg; base < end; base += kBlock) {
     const int n = (int)min((uint32_t)kBlock, end - base);
@@ -464,7 +502,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *_
 void launch_render_bwd(const ProjArgs &a, const Rec2 *rec, const uint2 *list,
                        const uint32_t *tile_start, const float *grad_image, float *slots,
                        hipStream_t s) {
-  int n = a.V * a.T;
+  const int n = a.V * a.T * a.parts;
   hipLaunchKernelGGL(k_render_bwd, dim3(n), dim3(kBlock), 0, s, a, rec, list, tile_start,
                      grad_image, slots);
 }
