@@ -59,7 +59,7 @@ struct gs_plan {
       p_list, p_slots, p_totals, p_part, p_scan_tmp, p_fpart;
   // voxelization
   Buf v_rec, v_count, v_offsets, v_scan_tmp, v_hist, v_tile_total, v_tile_start, v_list, v_slots,
-      v_totals;
+      v_totals, v_fpart;
   // losses
   Buf l_coef, l_part;
   // adaptive control and metrics
@@ -406,7 +406,17 @@ gs_status vox_bin(gs_plan *pl, const gs_gaussians *g, const gs_grid *grid, float
   a.layers = std::max(1, std::min(a.TZ, 4096 / plane));
   a.G = (a.TZ + a.layers - 1) / a.layers;
   a.Tg = plane * a.layers;
-  a.C = (int)((a.M + kChunk - 1) / kChunk);
+  // as for the projection: smaller chunks and several parts per tile list
+  // when a small grid (the TV block) would leave most of the chip idle
+  a.cpt = kChunkPerThread;
+  while (a.cpt > 1 && (int64_t)a.G * ((a.M + (int64_t)kBlock * a.cpt - 1) / ((int64_t)kBlock * a.cpt)) < 512)
+    a.cpt /= 2;
+  a.C = (int)((a.M + (int64_t)kBlock * a.cpt - 1) / ((int64_t)kBlock * a.cpt));
+  {
+    const int64_t tiles = (int64_t)a.G * a.Tg;
+    a.parts = tiles >= 4096 ? 1 : (int)std::min<int64_t>(16, (4096 + tiles - 1) / tiles);
+    a.bparts = tiles >= 1024 ? 1 : (int)std::min<int64_t>(16, (1024 + tiles - 1) / tiles);
+  }
   cutoff_consts(cutoff, a.kappa, a.thr, a.qmax);
   const int64_t GT = (int64_t)a.G * a.Tg, GC = (int64_t)a.G * a.C;
   const int64_t nb = (a.M + 4095) / 4096 + 1;
@@ -500,6 +510,7 @@ void gs_plan_destroy(gs_plan *p) {
                  &p->p_chunk_cnt, &p->p_chunk_start, &p->p_offsets, &p->p_list, &p->p_slots,
                  &p->p_totals, &p->p_part, &p->p_scan_tmp, &p->p_fpart, &p->v_rec, &p->v_count, &p->v_offsets, &p->v_scan_tmp, &p->v_hist,
                  &p->v_tile_total, &p->v_tile_start, &p->v_list, &p->v_slots, &p->v_totals,
+                 &p->v_fpart,
                  &p->l_coef, &p->l_part, &p->skipped, &p->d_action, &p->d_count, &p->d_offsets,
                  &p->d_scan_tmp, &p->d_totals, &p->m_sse, &p->m_max, &p->m_out, &p->m_stack,
                  &p->m_loss};
@@ -719,10 +730,17 @@ gs_status gs_voxelize_fwd(const gs_gaussians *g, const gs_grid *grid, float cuto
     return tp.owned ? sync_stream(plan, stream) : GS_OK;
   }
   GS_TRY(vox_bin(plan, g, grid, cutoff, stream));
+  float *partial = nullptr;
+  if (plan->vargs.parts > 1) {
+    GS_TRY(ensure(plan, plan->v_fpart,
+                  4 * (size_t)plan->vargs.parts * (size_t)plan->vargs.G * plan->vargs.Tg * 2 * kBlock,
+                  stream));
+    partial = P<float>(plan->v_fpart);
+  }
   {
     StageTimer t(plan, GS_STAGE_VOX_FWD, stream);
     launch_vox_fwd(plan->vargs, P<Rec3>(plan->v_rec), P<uint32_t>(plan->v_list),
-                   P<uint32_t>(plan->v_tile_start), volume, stream);
+                   P<uint32_t>(plan->v_tile_start), volume, partial, stream);
   }
   GS_TRY(check_launch("voxelize forward"));
   if (tp.owned) GS_TRY(sync_stream(plan, stream));

@@ -325,6 +325,9 @@ struct VoxArgs {
   int Tg;                  // tiles per group = TX * TY * layers
   int C;                   // chunks
   float kappa, thr, qmax;
+  int cpt;                 // Gaussians per thread per binning chunk (chunk = kBlock * cpt)
+  int parts;               // workgroups per tile list in the forward (>= 1)
+  int bparts;              // and in the backward (its per-batch setup favours fewer parts)
 };
 
 void launch_vox_records(const VoxArgs &a, Rec3 *rec, uint32_t *count,
@@ -334,8 +337,10 @@ void launch_scan_big(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *blo
 void launch_vox_hist(const VoxArgs &a, const Rec3 *rec, uint32_t *hist, hipStream_t s);
 void launch_vox_scatter(const VoxArgs &a, const Rec3 *rec, const uint32_t *hist,
                         const uint32_t *tile_start, uint32_t *list, hipStream_t s);
+// With a.parts > 1, partial [parts][G * Tg][512] holds each part's voxel sums,
+// added in part order by a second kernel.
 void launch_vox_fwd(const VoxArgs &a, const Rec3 *rec, const uint32_t *list,
-                    const uint32_t *tile_start, float *volume, hipStream_t s);
+                    const uint32_t *tile_start, float *volume, float *partial, hipStream_t s);
 void launch_vox_bwd(const VoxArgs &a, const Rec3 *rec, const uint32_t *list,
                     const uint32_t *tile_start, const uint32_t *offsets, const float *grad_volume,
                     float *slots, hipStream_t s);

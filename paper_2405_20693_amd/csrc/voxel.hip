@@ -90,8 +90,8 @@ __global__ __launch_bounds__(kBlock) void k_vox_hist(VoxArgs a, const Rec3 *__re
   for (int t = tid; t < a.Tg; t += kBlock) sh[t] = 0;
   __syncthreads();
   const int zl = grp * a.layers, zh = min(zl + a.layers, a.TZ) - 1;
-  const int64_t g0 = (int64_t)c * kChunk;
-  for (int k = 0; k < kChunkPerThread; ++k) {
+  const int64_t g0 = (int64_t)c * kBlock * a.cpt;
+  for (int k = 0; k < a.cpt; ++k) {
     int64_t g = g0 + (int64_t)k * kBlock + tid;
     if (g >= a.M) break;
     Box3 b = unpack_box(rec[g]);
@@ -122,8 +122,8 @@ __global__ __launch_bounds__(kBlock) void k_vox_scatter(VoxArgs a, const Rec3 *_
   for (int t = tid; t < a.Tg; t += kBlock) cur[t] = ts[t] + hp[t];
   __syncthreads();
   const int zl = grp * a.layers, zh = min(zl + a.layers, a.TZ) - 1;
-  const int64_t g0 = (int64_t)c * kChunk;
-  for (int k = 0; k < kChunkPerThread; ++k) {
+  const int64_t g0 = (int64_t)c * kBlock * a.cpt;
+  for (int k = 0; k < a.cpt; ++k) {
     int64_t g = g0 + (int64_t)k * kBlock + tid;
     if (g >= a.M) break;
     Box3 b = unpack_box(rec[g]);
@@ -190,9 +190,11 @@ __device__ inline float vox_q(const float (*s)[kBlock], int e, float dx, float d
 __global__ __launch_bounds__(kBlock) void k_vox_fwd(VoxArgs a, const Rec3 *__restrict__ rec,
                                                     const uint32_t *__restrict__ list,
                                                     const uint32_t *__restrict__ tile_start,
-                                                    float *__restrict__ vol) {
+                                                    float *__restrict__ vol,
+                                                    float *__restrict__ partial) {
   __shared__ float s[13][kBlock];
-  const int item = xcd_remap(blockIdx.x, gridDim.x);
+  const int wi = xcd_remap(blockIdx.x, gridDim.x);
+  const int item = wi / a.parts, part = wi - item * a.parts;
   const VoxTile T = decode_item(a, item);
   if (!T.valid) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -208,7 +210,8 @@ __global__ __launch_bounds__(kBlock) void k_vox_fwd(VoxArgs a, const Rec3 *__res
     vy[k] = (int)oy[k] + ((lane >> 2) & 3);
     vz[k] = (int)oz[k] + (lane >> 4);
   }
-  const uint32_t beg = tile_start[item], end = tile_start[item + 1];
+  uint32_t beg, end;
+  list_part(tile_start[item], tile_start[item + 1], part, a.parts, beg, end);
   for (uint32_t base = beg; base < end; base += kBlock) {
     const int n = (int)min((uint32_t)kBlock, end - base);
     __syncthreads();
@@ -231,15 +234,45 @@ __global__ __launch_bounds__(kBlock) void k_vox_fwd(VoxArgs a, const Rec3 *__res
       }
     }
   }
+  if (a.parts > 1) {
+    float *pp = partial + ((int64_t)part * a.G * a.Tg + item) * (2 * kBlock);
+    pp[tid] = acc[0];
+    pp[kBlock + tid] = acc[1];
+    return;
+  }
   for (int k = 0; k < 2; ++k)
     if (vx[k] < a.nx && vy[k] < a.ny && vz[k] < a.nz)
       vol[((int64_t)vz[k] * a.ny + vy[k]) * a.nx + vx[k]] = acc[k];
 }
 
+// Sum of the parts of each tile's voxels, in part order (same voxel mapping
+// as the forward: sub-cube w + 4k, lane).
+__global__ __launch_bounds__(kBlock) void k_vox_parts(VoxArgs a, const float *__restrict__ partial,
+                                                      float *__restrict__ vol) {
+  const int item = blockIdx.x;
+  const VoxTile T = decode_item(a, item);
+  if (!T.valid) return;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t stride = (int64_t)a.G * a.Tg * (2 * kBlock);
+  for (int k = 0; k < 2; ++k) {
+    const int sc = w + 4 * k;
+    const int vx = T.tx * kVTile + (sc & 1) * kVSub + (lane & 3);
+    const int vy = T.ty * kVTile + ((sc >> 1) & 1) * kVSub + ((lane >> 2) & 3);
+    const int vz = T.tz * kVTile + (sc >> 2) * kVSub + (lane >> 4);
+    const float *p = partial + (int64_t)item * (2 * kBlock) + k * kBlock + tid;
+    float acc = 0.f;
+    for (int j = 0; j < a.parts; ++j) acc += p[j * stride];
+    if (vx < a.nx && vy < a.ny && vz < a.nz) vol[((int64_t)vz * a.ny + vy) * a.nx + vx] = acc;
+  }
+}
+
 void launch_vox_fwd(const VoxArgs &a, const Rec3 *rec, const uint32_t *list,
-                    const uint32_t *tile_start, float *volume, hipStream_t s) {
-  int n = a.G * a.Tg;
-  hipLaunchKernelGGL(k_vox_fwd, dim3(n), dim3(kBlock), 0, s, a, rec, list, tile_start, volume);
+                    const uint32_t *tile_start, float *volume, float *partial, hipStream_t s) {
+  const int n = a.G * a.Tg * a.parts;
+  hipLaunchKernelGGL(k_vox_fwd, dim3(n), dim3(kBlock), 0, s, a, rec, list, tile_start, volume,
+                     partial);
+  if (a.parts > 1)
+    hipLaunchKernelGGL(k_vox_parts, dim3(a.G * a.Tg), dim3(kBlock), 0, s, a, partial, volume);
 }
 
 // -------------------------------------------------------------- backward --
@@ -257,7 +290,8 @@ __global__ __launch_bounds__(kBlock) void k_vox_bwd(VoxArgs a, const Rec3 *__res
   __shared__ float s_H[kVTile * kVTile * kVTile];
   __shared__ float s_acc[4][10][kBlock];
   __shared__ uint16_t s_q[4][kBlock];
-  const int item = xcd_remap(blockIdx.x, gridDim.x);
+  const int wi = xcd_remap(blockIdx.x, gridDim.x);
+  const int item = wi / a.bparts, part = wi - item * a.bparts;
   const VoxTile T = decode_item(a, item);
   if (!T.valid) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -266,7 +300,8 @@ __global__ __launch_bounds__(kBlock) void k_vox_bwd(VoxArgs a, const Rec3 *__res
     const int x = T.tx * kVTile + lx, y = T.ty * kVTile + ly, z = T.tz * kVTile + lz;
     s_H[i] = (x < a.nx && y < a.ny && z < a.nz) ? grad_vol[((int64_t)z * a.ny + y) * a.nx + x] : 0.f;
   }
-  const uint32_t beg = tile_start[item], end = tile_start[item + 1];
+  uint32_t beg, end;
+  list_part(tile_start[item], tile_start[item + 1], part, a.bparts, beg, end);
   for (uint32_t base = beg; base < end; base += kBlock) {
     const int n = (int)min((uint32_t)kBlock, end - base);
     __syncthreads();
@@ -349,7 +384,7 @@ __global__ __launch_bounds__(kBlock) void k_vox_bwd(VoxArgs a, const Rec3 *__res
 void launch_vox_bwd(const VoxArgs &a, const Rec3 *rec, const uint32_t *list,
                     const uint32_t *tile_start, const uint32_t *offsets, const float *grad_volume,
                     float *slots, hipStream_t s) {
-  int n = a.G * a.Tg;
+  const int n = a.G * a.Tg * a.bparts;
   hipLaunchKernelGGL(k_vox_bwd, dim3(n), dim3(kBlock), 0, s, a, rec, list, tile_start, offsets,
                      grad_volume, slots);
 }
