@@ -64,7 +64,7 @@ struct gs_plan {
   Buf l_coef, l_part;
   // adaptive control and metrics
   Buf d_action, d_count, d_offsets, d_scan_tmp, d_totals, m_sse, m_max, m_out, m_stack, m_loss;
-  Buf skipped;  // unsigned long long [2]: projection, voxelization
+  Buf skipped;  // unsigned long long [4]: running projection, voxelization; last call's two
   // host side
   gs_view *stage = nullptr;          // pinned staging of per-view constants
   size_t stage_cap = 0;
@@ -170,11 +170,22 @@ gs_status ensure(gs_plan *pl, Buf &b, size_t bytes, hipStream_t s) {
   return GS_OK;
 }
 
-// Two skipped counters (projection, voxelization); both start at zero.
+// Skipped-Gaussian counters: the binning kernels add to the running counter
+// of their operator (0 projection, 1 voxelization) and the scatter kernel of
+// the same call moves it to the last-call slot (2, 3) and clears it, so no
+// fill is needed per call.  All four start at zero.
 gs_status ensure_skipped(gs_plan *pl, hipStream_t s) {
   if (pl->skipped.p) return GS_OK;
-  GS_TRY(ensure(pl, pl->skipped, 16, s));
-  if (hipMemsetAsync(pl->skipped.p, 0, 16, s) != hipSuccess) return fail(GS_EHIP, "hipMemsetAsync");
+  GS_TRY(ensure(pl, pl->skipped, 32, s));
+  if (hipMemsetAsync(pl->skipped.p, 0, 32, s) != hipSuccess) return fail(GS_EHIP, "hipMemsetAsync");
+  return GS_OK;
+}
+
+// Clears a running counter when a call stops between binning and scatter.
+gs_status clear_running_skipped(gs_plan *pl, int which, hipStream_t s) {
+  if (hipMemsetAsync(reinterpret_cast<unsigned long long *>(pl->skipped.p) + which, 0, 8, s) !=
+      hipSuccess)
+    return fail(GS_EHIP, "hipMemsetAsync");
   return GS_OK;
 }
 
@@ -349,33 +360,49 @@ gs_status proj_bin(gs_plan *pl, const gs_gaussians *g, const gs_view *views, int
   GS_TRY(ensure(pl, pl->p_offsets, 4 * VM, s));
   GS_TRY(ensure(pl, pl->p_totals, 16, s));
   GS_TRY(ensure_skipped(pl, s));
-  if (hipMemsetAsync(pl->skipped.p, 0, 8, s) != hipSuccess) return fail(GS_EHIP, "hipMemsetAsync");
   StageTimer t_bin(pl, GS_STAGE_PROJ_BIN, s);
   launch_proj_hist(a, P<Rec2>(pl->p_rec), P<uint32_t>(pl->p_hist), P<uint32_t>(pl->p_chunk_cnt),
                    P<unsigned long long>(pl->skipped), s);
   launch_hist_colscan(nv, a.C, a.T, P<uint32_t>(pl->p_hist), P<uint32_t>(pl->p_tile_total), s);
-  // block-sum scratch of the two multi-block scans: 2 * ceil(n / 4096) + 1 entries each
-  const int64_t tmp_t = 2 * ((VT + 4095) / 4096) + 1, tmp_c = 2 * ((VC + 4095) / 4096) + 1;
-  GS_TRY(ensure(pl, pl->p_scan_tmp, 4 * (size_t)(tmp_t + tmp_c), s));
-  launch_scan_big(P<uint32_t>(pl->p_tile_total), P<uint32_t>(pl->p_tile_start), VT,
-                  P<uint32_t>(pl->p_scan_tmp), P<unsigned long long>(pl->p_totals), s);
-  launch_scan_big(P<uint32_t>(pl->p_chunk_cnt), P<uint32_t>(pl->p_chunk_start), VC,
-                  P<uint32_t>(pl->p_scan_tmp) + tmp_t, P<unsigned long long>(pl->p_totals) + 1, s);
+  if (VT <= 32768 && VC <= 32768) {
+    // both scans by one workgroup each, in one launch
+    launch_scan2(P<uint32_t>(pl->p_tile_total), P<uint32_t>(pl->p_tile_start), (int)VT,
+                 P<uint32_t>(pl->p_chunk_cnt), P<uint32_t>(pl->p_chunk_start), (int)VC,
+                 P<unsigned long long>(pl->p_totals), s);
+  } else {
+    // block-sum scratch of the two multi-block scans: 2 * ceil(n / 4096) + 1 entries each
+    const int64_t tmp_t = 2 * ((VT + 4095) / 4096) + 1, tmp_c = 2 * ((VC + 4095) / 4096) + 1;
+    GS_TRY(ensure(pl, pl->p_scan_tmp, 4 * (size_t)(tmp_t + tmp_c), s));
+    launch_scan_big(P<uint32_t>(pl->p_tile_total), P<uint32_t>(pl->p_tile_start), VT,
+                    P<uint32_t>(pl->p_scan_tmp), P<unsigned long long>(pl->p_totals), s);
+    launch_scan_big(P<uint32_t>(pl->p_chunk_cnt), P<uint32_t>(pl->p_chunk_start), VC,
+                    P<uint32_t>(pl->p_scan_tmp) + tmp_t, P<unsigned long long>(pl->p_totals) + 1, s);
+  }
   t_bin.stop();
   GS_TRY(check_launch("projection binning"));
   if (hipMemcpyAsync(pl->readback, pl->p_totals.p, 16, hipMemcpyDeviceToHost, s) != hipSuccess)
     return fail(GS_EHIP, "entry count readback failed");
   GS_TRY(sync_stream(pl, s));
   const unsigned long long entries = pl->readback[0];
-  if (entries != pl->readback[1])
+  if (entries != pl->readback[1]) {
+    (void)clear_running_skipped(pl, 0, s);
     return fail(GS_EHIP, "internal error: tile and Gaussian entry totals differ");
-  if (entries >= 0xffffffffull)
+  }
+  if (entries >= 0xffffffffull) {
+    (void)clear_running_skipped(pl, 0, s);
     return fail(GS_EOVERFLOW, "more than 2^32-1 tile entries: split the views over several calls");
-  GS_TRY(ensure(pl, pl->p_list, 8 * (size_t)entries, s));
+  }
+  {
+    gs_status st = ensure(pl, pl->p_list, 8 * (size_t)entries, s);
+    if (st != GS_OK) {
+      (void)clear_running_skipped(pl, 0, s);
+      return st;
+    }
+  }
   StageTimer t_sc(pl, GS_STAGE_PROJ_SCATTER, s);
   launch_proj_scatter(a, P<Rec2>(pl->p_rec), P<uint32_t>(pl->p_hist), P<uint32_t>(pl->p_tile_start),
                       P<uint32_t>(pl->p_chunk_start), P<uint2>(pl->p_list),
-                      P<uint32_t>(pl->p_offsets), s);
+                      P<uint32_t>(pl->p_offsets), P<unsigned long long>(pl->skipped), s);
   t_sc.stop();
   GS_TRY(check_launch("projection scatter"));
   pl->pargs = a;
@@ -429,8 +456,6 @@ gs_status vox_bin(gs_plan *pl, const gs_gaussians *g, const gs_grid *grid, float
   GS_TRY(ensure(pl, pl->v_tile_start, 4 * (size_t)(GT + 1), s));
   GS_TRY(ensure(pl, pl->v_totals, 16, s));
   GS_TRY(ensure_skipped(pl, s));
-  if (hipMemsetAsync(P<unsigned long long>(pl->skipped) + 1, 0, 8, s) != hipSuccess)
-    return fail(GS_EHIP, "hipMemsetAsync");
   StageTimer t_bin(pl, GS_STAGE_VOX_BIN, s);
   launch_vox_records(a, P<Rec3>(pl->v_rec), P<uint32_t>(pl->v_count),
                      P<unsigned long long>(pl->skipped) + 1, s);
@@ -446,13 +471,24 @@ gs_status vox_bin(gs_plan *pl, const gs_gaussians *g, const gs_grid *grid, float
     return fail(GS_EHIP, "entry count readback failed");
   GS_TRY(sync_stream(pl, s));
   const unsigned long long entries = pl->readback[0];
-  if (entries != pl->readback[1])
+  if (entries != pl->readback[1]) {
+    (void)clear_running_skipped(pl, 1, s);
     return fail(GS_EHIP, "internal error: tile and Gaussian entry totals differ");
-  if (entries >= 0xffffffffull) return fail(GS_EOVERFLOW, "more than 2^32-1 voxel tile entries");
-  GS_TRY(ensure(pl, pl->v_list, 4 * (size_t)entries, s));
+  }
+  if (entries >= 0xffffffffull) {
+    (void)clear_running_skipped(pl, 1, s);
+    return fail(GS_EOVERFLOW, "more than 2^32-1 voxel tile entries");
+  }
+  {
+    gs_status st = ensure(pl, pl->v_list, 4 * (size_t)entries, s);
+    if (st != GS_OK) {
+      (void)clear_running_skipped(pl, 1, s);
+      return st;
+    }
+  }
   StageTimer t_sc(pl, GS_STAGE_VOX_SCATTER, s);
   launch_vox_scatter(a, P<Rec3>(pl->v_rec), P<uint32_t>(pl->v_hist), P<uint32_t>(pl->v_tile_start),
-                     P<uint32_t>(pl->v_list), s);
+                     P<uint32_t>(pl->v_list), P<unsigned long long>(pl->skipped), s);
   t_sc.stop();
   GS_TRY(check_launch("voxel scatter"));
   pl->vargs = a;
@@ -533,10 +569,10 @@ gs_status gs_plan_status(gs_plan *p, int64_t *skipped, int64_t *tile_entries) {
                                     (int64_t)(p->v_valid ? p->v_entries : 0);
   if (!p->used || !p->skipped.p) return GS_OK;
   GS_TRY(sync_stream(p, p->last_stream));
-  unsigned long long h[2] = {0, 0};
+  unsigned long long h[4] = {0, 0, 0, 0};
   if (hipMemcpy(h, p->skipped.p, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
     return fail(GS_EHIP, "status readback failed");
-  if (skipped) *skipped = (int64_t)(h[0] + h[1]);
+  if (skipped) *skipped = (int64_t)(h[2] + h[3]);
   return GS_OK;
 }
 

@@ -289,9 +289,11 @@ void launch_hist_colscan(int groups, int C, int T, uint32_t *hist, uint32_t *til
 void launch_scan2(const uint32_t *in0, uint32_t *out0, int n0, const uint32_t *in1, uint32_t *out1,
                   int n1, unsigned long long *totals, hipStream_t s);
 // Tile-list entries are (Gaussian index, backward slot) pairs.
+// skipped [4]: the scatter moves the running projection count (0) to the
+// last-call slot (2) and clears it.
 void launch_proj_scatter(const ProjArgs &a, const Rec2 *rec, const uint32_t *hist,
                          const uint32_t *tile_start, const uint32_t *chunk_start, uint2 *list,
-                         uint32_t *offsets, hipStream_t s);
+                         uint32_t *offsets, unsigned long long *skipped, hipStream_t s);
 // With a.parts > 1, each part of a tile list writes its pixel sums to
 // partial [parts][V * T][256] and a second kernel adds the parts in order.
 void launch_render_fwd(const ProjArgs &a, const Rec2 *rec, const uint2 *list,
@@ -335,8 +337,10 @@ void launch_vox_records(const VoxArgs &a, Rec3 *rec, uint32_t *count,
 void launch_scan_big(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *block_tmp,
                      unsigned long long *total, hipStream_t s);
 void launch_vox_hist(const VoxArgs &a, const Rec3 *rec, uint32_t *hist, hipStream_t s);
+// skipped [4]: moves the running voxelization count (1) to slot 3, clears it.
 void launch_vox_scatter(const VoxArgs &a, const Rec3 *rec, const uint32_t *hist,
-                        const uint32_t *tile_start, uint32_t *list, hipStream_t s);
+                        const uint32_t *tile_start, uint32_t *list, unsigned long long *skipped,
+                        hipStream_t s);
 // With a.parts > 1, partial [parts][G * Tg][512] holds each part's voxel sums,
 // added in part order by a second kernel.
 void launch_vox_fwd(const VoxArgs &a, const Rec3 *rec, const uint32_t *list,

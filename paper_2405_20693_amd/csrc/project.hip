@@ -197,10 +197,15 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
                                                          const uint32_t *__restrict__ tile_start,
                                                          const uint32_t *__restrict__ chunk_start,
                                                          uint2 *__restrict__ list,
-                                                         uint32_t *__restrict__ offsets) {
+                                                         uint32_t *__restrict__ offsets,
+                                                         unsigned long long *skipped) {
   extern __shared__ uint32_t cur[];
   __shared__ uint32_t sh4[4];
   const int c = blockIdx.x, v = blockIdx.y, tid = threadIdx.x;
+  if (c == 0 && v == 0 && tid == 0) {  // the binning kernel of this call has finished
+    skipped[2] = skipped[0];
+    skipped[0] = 0ull;
+  }
   const uint32_t *h = hist + ((int64_t)v * a.C + c) * a.T;
   const uint32_t *ts = tile_start + (int64_t)v * a.T;
   for (int t = tid; t < a.T; t += kBlock) cur[t] = ts[t] + h[t];
@@ -233,10 +238,10 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
 
 void launch_proj_scatter(const ProjArgs &a, const Rec2 *rec, const uint32_t *hist,
                          const uint32_t *tile_start, const uint32_t *chunk_start, uint2 *list,
-                         uint32_t *offsets, hipStream_t s) {
+                         uint32_t *offsets, unsigned long long *skipped, hipStream_t s) {
   dim3 grid(a.C, a.V);
   hipLaunchKernelGGL(k_proj_scatter, grid, dim3(kBlock), a.T * sizeof(uint32_t), s, a, rec, hist,
-                     tile_start, chunk_start, list, offsets);
+                     tile_start, chunk_start, list, offsets, skipped);
 }
 
 // ------------------------------------------------------- render forward --

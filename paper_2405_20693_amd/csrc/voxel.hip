@@ -114,9 +114,14 @@ void launch_vox_hist(const VoxArgs &a, const Rec3 *rec, uint32_t *hist, hipStrea
 __global__ __launch_bounds__(kBlock) void k_vox_scatter(VoxArgs a, const Rec3 *__restrict__ rec,
                                                         const uint32_t *__restrict__ hist,
                                                         const uint32_t *__restrict__ tile_start,
-                                                        uint32_t *__restrict__ list) {
+                                                        uint32_t *__restrict__ list,
+                                                        unsigned long long *skipped) {
   extern __shared__ uint32_t cur[];
   const int c = blockIdx.x, grp = blockIdx.y, tid = threadIdx.x;
+  if (c == 0 && grp == 0 && tid == 0) {  // the record kernel of this call has finished
+    skipped[3] = skipped[1];
+    skipped[1] = 0ull;
+  }
   const uint32_t *hp = hist + ((int64_t)grp * a.C + c) * a.Tg;
   const uint32_t *ts = tile_start + (int64_t)grp * a.Tg;
   for (int t = tid; t < a.Tg; t += kBlock) cur[t] = ts[t] + hp[t];
@@ -139,9 +144,10 @@ __global__ __launch_bounds__(kBlock) void k_vox_scatter(VoxArgs a, const Rec3 *_
 }
 
 void launch_vox_scatter(const VoxArgs &a, const Rec3 *rec, const uint32_t *hist,
-                        const uint32_t *tile_start, uint32_t *list, hipStream_t s) {
+                        const uint32_t *tile_start, uint32_t *list, unsigned long long *skipped,
+                        hipStream_t s) {
   hipLaunchKernelGGL(k_vox_scatter, dim3(a.C, a.G), dim3(kBlock), a.Tg * sizeof(uint32_t), s, a,
-                     rec, hist, tile_start, list);
+                     rec, hist, tile_start, list, skipped);
 }
 
 // --------------------------------------------------------------- forward --
