@@ -510,6 +510,10 @@ struct TempPlan {
 
 }  // namespace
 
+namespace gsk {
+void set_last_error(const char *msg) { g_err = msg; }
+}  // namespace gsk
+
 extern "C" {
 
 const char *gs_last_error(void) { return g_err.c_str(); }

@@ -366,6 +366,9 @@ int tv_num_blocks(int nx, int ny, int nz);
 
 // ------------------------------------------------------ training loop --
 
+// Sets the message gs_last_error returns (for errors found outside api.hip).
+void set_last_error(const char *msg);
+
 struct AdamArgs {
   float *raw[4];         // mean, log_scale, quat, density_raw
   float *m[4], *v[4];

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/gs_train.h"
+#include "internal.h"
 
 namespace {
 
@@ -86,6 +87,11 @@ template <class T> gs_status grow(T *&p, size_t &cap, size_t want) {
     gs_status _st = (x);          \
     if (_st != GS_OK) return _st; \
   } while (0)
+
+gs_status invalid(const char *msg) {
+  gsk::set_last_error(msg);
+  return GS_EINVAL;
+}
 
 }  // namespace
 
@@ -183,9 +189,12 @@ gs_status step(gs_trainer *t, const int32_t *view_idx, const int32_t *tv_offset,
   const int B = c.views_per_iter;
   const int W = t->views[0].width, H = t->views[0].height;
   const size_t img = (size_t)W * H;
+  if (densify_due(c, t->iter + 1) && !normals)
+    return invalid("this iteration densifies: the split draws (normals) are required");
   t->batch.resize(B);
   for (int b = 0; b < B; ++b) {
-    if (view_idx[b] < 0 || view_idx[b] >= (int32_t)t->views.size()) return GS_EINVAL;
+    if (view_idx[b] < 0 || view_idx[b] >= (int32_t)t->views.size())
+      return invalid("view index out of range");
     t->batch[b] = t->views[view_idx[b]];
   }
   const int D = c.tv_size;
@@ -196,7 +205,8 @@ gs_status step(gs_trainer *t, const int32_t *view_idx, const int32_t *tv_offset,
     int bd[3];
     for (int k = 0; k < 3; ++k) {
       bd[k] = std::min(D, dims[k]);
-      if (tv_offset[k] < 0 || tv_offset[k] > dims[k] - bd[k]) return GS_EINVAL;
+      if (tv_offset[k] < 0 || tv_offset[k] > dims[k] - bd[k])
+        return invalid("TV block offset outside the grid");
       block.origin[k] = t->grid.origin[k] + (float)tv_offset[k] * t->grid.spacing[k];
       block.spacing[k] = t->grid.spacing[k];
     }
@@ -246,10 +256,7 @@ gs_status step(gs_trainer *t, const int32_t *view_idx, const int32_t *tv_offset,
                     (float)(c.lr_density * f), it1};
   TR_TRY(gs_adam_step(&t->sets[t->cur].p, t->n, &gr, &ac, t->stream));
   t->iter = it1;
-  if (densify_due(c, it1)) {
-    if (!normals) return GS_EINVAL;
-    TR_TRY(densify(t, normals));
-  }
+  if (densify_due(c, it1)) TR_TRY(densify(t, normals));
   return GS_OK;
 }
 
@@ -302,18 +309,20 @@ void gs_trainer_destroy(gs_trainer *t) {
 gs_status gs_trainer_create(const gs_train_config *cfg, const gs_gaussians *init,
                             const float *measured, const gs_view *views, int32_t n_views,
                             const gs_grid *grid, gs_trainer **out) {
-  if (!out) return GS_EINVAL;
+  if (!out) return invalid("out is NULL");
   *out = nullptr;
-  if (!cfg || !init || !measured || !views || n_views < 1 || !grid) return GS_EINVAL;
+  if (!cfg || !init || !measured || !views || n_views < 1 || !grid)
+    return invalid("NULL argument or no views");
   if (cfg->iterations < 1 || cfg->views_per_iter < 1 || cfg->views_per_iter > n_views ||
       cfg->tv_size < 0 || !(cfg->cutoff > 0.f) || !(cfg->lr_final_ratio > 0.f) ||
       cfg->densify_interval < 0)
-    return GS_EINVAL;
+    return invalid("invalid training configuration");
   if (init->n < 0 || (init->n > 0 && (!init->mean || !init->scale || !init->quat || !init->density)))
-    return GS_EINVAL;
+    return invalid("initial Gaussians incomplete");
   for (int i = 1; i < n_views; ++i)
-    if (views[i].width != views[0].width || views[i].height != views[0].height) return GS_EINVAL;
-  if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1) return GS_EINVAL;
+    if (views[i].width != views[0].width || views[i].height != views[0].height)
+      return invalid("views differ in detector size");
+  if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1) return invalid("grid size must be >= 1");
   gs_trainer *t = new (std::nothrow) gs_trainer();
   if (!t) return GS_ENOMEM;
   t->cfg = *cfg;

@@ -220,10 +220,12 @@ def _small_problem(seed=19, m=800, n_views=6, det=48):
     return wl
 
 
-def test_trainer_first_iteration_matches_oracle(ops, tr):
-    """One trainer iteration (explicit view and TV block) against the oracle's
-    composition: image loss on the view, TV of the block, their gradients
-    through the projection and voxelizer, then one Adam step."""
+@pytest.mark.parametrize("vidx,lambda_tv", [([4, 1], 0.05), ([0, 5, 2], 0.0), ([3], 0.05)])
+def test_trainer_first_iteration_matches_oracle(ops, tr, vidx, lambda_tv):
+    """One trainer iteration (explicit views and TV block) against the
+    oracle's composition: image loss on the views, TV of the block, their
+    gradients through the projection and voxelizer, then one Adam step.  Covers
+    one view, a batch of views (measured images gathered) and no TV term."""
     wl = _small_problem()
     g = wl.gaussians
     views = ops.Views.from_scan(wl.scan)
@@ -231,23 +233,28 @@ def test_trainer_first_iteration_matches_oracle(ops, tr):
     measured = workloads.measured_projections(wl)
     grid = Grid(40, 40, 40, (-1.0, -1.0, -1.0), (0.05, 0.05, 0.05))
     D = 12
-    cfg = dict(iterations=100, densify_from=10 ** 6, tv_size=D, views_per_iter=2)
+    cfg = dict(iterations=100, densify_from=10 ** 6, tv_size=D, views_per_iter=len(vidx),
+               lambda_tv=lambda_tv)
     trainer = tr.Trainer(*_gdev(g), _dev(measured), views, grid, **cfg)
-    vidx, off = [4, 1], (7, 20, 3)
+    off = (7, 20, 3)
     loss = trainer.step(vidx, off)
+    assert trainer.iteration() == 1
     mean, scale, quat, dens = (t.cpu().numpy().astype(np.float64) for t in trainer.model())
     trainer.close()
     # oracle composition
     oviews = [ov[i] for i in vidx]
     img = oracle.project(g, oviews)["image"]
     total, l1, s, gimg = oracle.image_loss(img.astype(np.float32), measured[vidx], 0.25)
-    block = Grid(D, D, D, tuple(grid.origin[k] + off[k] * grid.spacing[k] for k in range(3)),
-                 grid.spacing)
-    vol = oracle.voxelize(g, block)["volume"]
-    tv, gvol = oracle.tv_loss(vol.astype(np.float32), 0.05)
-    assert abs(loss - (total + 0.05 * tv)) <= 1e-4 * abs(total + 0.05 * tv)
     gp = oracle.project_grad(g, oviews, gimg)
-    gv = oracle.voxelize_grad(g, block, gvol)
+    if lambda_tv > 0:
+        block = Grid(D, D, D, tuple(grid.origin[k] + off[k] * grid.spacing[k] for k in range(3)),
+                     grid.spacing)
+        vol = oracle.voxelize(g, block)["volume"]
+        tv, gvol = oracle.tv_loss(vol.astype(np.float32), lambda_tv)
+        gv = oracle.voxelize_grad(g, block, gvol)
+    else:
+        tv, gv = 0.0, {k: 0.0 for k in KEYS}
+    assert abs(loss - (total + lambda_tv * tv)) <= 1e-4 * abs(total + lambda_tv * tv)
     grad = {k: gp[k] + gv[k] for k in KEYS}
     raw = {"mean": g.mean.astype(np.float64), "scale": np.log(g.scale.astype(np.float64)),
            "quat": g.quat.astype(np.float64), "density": ot.softplus_inv(g.density.astype(np.float64))}
@@ -265,6 +272,40 @@ def test_trainer_first_iteration_matches_oracle(ops, tr):
         print(k, "elements off", int(bad.sum()), "of", bad.size, flush=True)
         assert not bad.any(), k
         assert (np.abs(d_got) <= lrs[k] * 1.001 + 4 * 2.0 ** -23 * np.abs(raw[k])).all()
+
+
+def test_trainer_explicit_densify_step(ops, tr):
+    """A step that is due to densify needs the split draws; with them the
+    model changes size as the adaptive control decides, and stays finite."""
+    wl = _small_problem(m=1500)
+    views = ops.Views.from_scan(wl.scan)
+    measured = _dev(workloads.measured_projections(wl))
+    grid = Grid(40, 40, 40, (-1.0, -1.0, -1.0), (0.05, 0.05, 0.05))
+    trainer = tr.Trainer(*_gdev(wl.gaussians), measured, views, grid, iterations=100, tv_size=8,
+                         densify_from=1, densify_interval=2, grad_threshold=1e-6,
+                         min_density=1e-3)
+    trainer.step([0], (0, 0, 0))                       # iteration 1: no densification
+    n = trainer.count()
+    from paper_2405_20693_amd import _native as N
+    with pytest.raises(N.GsError):
+        trainer.step([1], (0, 0, 0))                   # iteration 2 densifies: draws missing
+    trainer.close()
+    trainer = tr.Trainer(*_gdev(wl.gaussians), measured, views, grid, iterations=100, tv_size=8,
+                         densify_from=1, densify_interval=2, grad_threshold=1e-6,
+                         min_density=1e-3)
+    trainer.step([0], (0, 0, 0))
+    normals = _dev(np.random.default_rng(3).standard_normal((n, 2, 3)).astype(np.float32))
+    trainer.step([1], (5, 5, 5), normals)
+    n2 = trainer.count()
+    mean, scale, quat, dens = trainer.model()
+    print(f"densify step: {n} -> {n2} Gaussians", flush=True)
+    assert n2 > n                                      # tiny threshold: most Gaussians grow
+    for t in (mean, scale, quat, dens):
+        assert torch.isfinite(t).all()
+    assert (scale > 0).all() and (dens > 0).all()
+    vol, none = trainer.evaluate(grid)
+    assert none is None and torch.isfinite(vol).all()
+    trainer.close()
 
 
 def _phantom_problem(n_views=24, det=96, m=6000, seed=21):
