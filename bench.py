@@ -11,6 +11,7 @@ in libgs.so.
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,6 +25,25 @@ sys.path.insert(0, ROOT)
 SLOTS_PER_PAIR = {"render_fwd": 10 + 4, "render_bwd": 18 + 4}
 PEAK_SLOTS_PER_S = 256 * 128 * 2.4e9       # CUs x FP32 lanes per clock x clock (157.3 TFLOP/s / 2)
 HBM_PEAK_GBS = 8000.0
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "c3_iteration_hbm_traffic.json")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    profile (FETCH_SIZE + WRITE_SIZE, calibrated), or None if there is none or
+    the kernel sources have changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            prof = json.load(f)
+        for rel, digest in prof["sources_sha256"].items():
+            with open(os.path.join(ROOT, rel), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != digest:
+                    return None
+        return prof["bytes_per_launch"].get(kernel)
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -289,7 +309,7 @@ def main():
             peak = PEAK_SLOTS_PER_S / 1e12
             roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
                         "peak": round(peak, 2), "unit": "TOP/s", "frac": round(achieved / peak, 4),
-                        "traffic": None, "pairs_per_launch": pairs,
+                        "traffic": measured_traffic(dom), "pairs_per_launch": pairs,
                         "ops_per_pair": SLOTS_PER_PAIR[dom], "avg_launch_ms": round(avg[dom], 4)}
 
     cpu = None
