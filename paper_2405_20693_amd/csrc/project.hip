@@ -262,7 +262,8 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
                                                        float *__restrict__ image,
                                                        float *__restrict__ partial) {
   __shared__ float4 s_r0[kBlock], s_r1[kBlock];
-  __shared__ float4 s_k0[4][64], s_k1[4][64];
+  // per wave: the kept records' coefficients, compacted, two float4 each
+  __shared__ float4 s_k[4][64][2];
   const int wi = xcd_remap(blockIdx.x, gridDim.x);
   const int item = wi / a.parts, part = wi - item * a.parts;
   const int v = item / a.T, t = item - v * a.T;
@@ -292,6 +293,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
     for (int c0 = 0; c0 < n; c0 += 64) {
       const int i = c0 + lane;
       bool hit = false;
+      float4 k0, k1;
       if (i < n) {
         const float4 r0 = s_r0[i], r1 = s_r1[i];
         const float c00 = r0.z, c01 = r0.w, c11 = r1.x, rho = r1.y;
@@ -305,22 +307,29 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
           const float K0 = u * (c00 * u + c01 * vv) + c11 * vv * vv + lr;
           const float K1 = -(2.f * c00 * u + c01 * vv);
           const float K2 = -(c01 * u + 2.f * c11 * vv);
-          s_k0[w][lane] = make_float4(K0, K1, K2, c00);
-          s_k1[w][lane] = make_float4(c01, c11, thr + lr, rho > 0.f ? 1.f : -1.f);
+          k0 = make_float4(K0, K1, K2, c00);
+          k1 = make_float4(c01, c11, thr + lr, rho > 0.f ? 1.f : -1.f);
         }
+      }
+      // compact the kept records to consecutive slots; an odd count is padded
+      // with a record whose threshold no q reaches (it adds exactly 0)
+      const uint64_t mask = __ballot(hit);
+      const int nk = __popcll(mask);
+      if (hit) {
+        const int pos = lanes_below(mask);
+        s_k[w][pos][0] = k0;
+        s_k[w][pos][1] = k1;
+      }
+      if ((nk & 1) && lane == 0) {
+        s_k[w][nk][0] = make_float4(0.f, 0.f, 0.f, 0.f);
+        s_k[w][nk][1] = make_float4(0.f, 0.f, INFINITY, 0.f);
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      uint64_t mask = __ballot(hit);
-      while (mask) {
-        const int j0 = __builtin_ctzll(mask);
-        mask &= mask - 1;
-        const bool two = mask != 0;
-        const int j1 = two ? __builtin_ctzll(mask) : j0;
-        if (two) mask &= mask - 1;
-        const float4 a0 = s_k0[w][j0], a1 = s_k1[w][j0];
-        const float4 b0 = s_k0[w][j1], b1 = s_k1[w][j1];
+      const float4 *kp = &s_k[w][0][0];
+      for (int k = 0; k < nk; k += 2, kp += 4) {
+        const float4 a0 = kp[0], a1 = kp[1], b0 = kp[2], b1 = kp[3];
         {
           float q = fmaf(a0.y, lx, a0.x);
           q = fmaf(a0.z, ly, q);
@@ -336,7 +345,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
           q = fmaf(b0.w, lxx, q);
           q = fmaf(b1.x, lxy, q);
           q = fmaf(b1.y, lyy, q);
-          const float e = (two && q >= b1.z) ? __builtin_amdgcn_exp2f(q) : 0.f;
+          const float e = (q >= b1.z) ? __builtin_amdgcn_exp2f(q) : 0.f;
           acc1 = fmaf(b1.w, e, acc1);
         }
       }
@@ -457,16 +466,19 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *_
       const float pu = s_pu[e], pv = s_pv[e];
       const float c00 = s_c00[e], c01 = s_c01[e], c11 = s_c11[e];
       const float dd = 2.f * c00;
-      float S0 = 0.f, S1 = 0.f, S2 = 0.f, S3 = 0.f, S4 = 0.f, S5 = 0.f;
       const float dx0 = rx0 - pu;
       const float thr = a.thr;
+      // per-column sums over the rows of G e, G e dy, G e dy^2; the x moments
+      // follow from them once per walk (dx is constant down a column)
+      float C0[kSub], C2[kSub], C5[kSub];
+#pragma unroll
+      for (int col = 0; col < kSub; ++col) C0[col] = C2[col] = C5[col] = 0.f;
 #pragma unroll 2
       for (int r = 0; r < kSub; ++r) {
         const float dy = ry0 + (float)r - pv;
-        float dx = dx0;
-        float q = dx * (c00 * dx + c01 * dy) + c11 * dy * dy;
-        float d = c00 * (2.f * dx + 1.f) + c01 * dy;
-        float R0 = 0.f, R1 = 0.f, R3 = 0.f;
+        const float dy2 = dy * dy;
+        float q = dx0 * (c00 * dx0 + c01 * dy) + c11 * dy2;
+        float d = c00 * (2.f * dx0 + 1.f) + c01 * dy;
         const float4 *Grow = reinterpret_cast<const float4 *>(s_G + (syl + r) * kTile + sxl);
         const float4 ga = Grow[0], gb = Grow[1];
         const float Gr[kSub] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
@@ -474,20 +486,24 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *_
         for (int col = 0; col < kSub; ++col) {
           const float ex = __builtin_amdgcn_exp2f(q) * Gr[col];
           const float ge = (q >= thr) ? ex : 0.f;
-          R0 += ge;
-          const float tt = ge * dx;
-          R1 += tt;
-          R3 = fmaf(tt, dx, R3);
+          C0[col] += ge;
+          C2[col] = fmaf(ge, dy, C2[col]);
+          C5[col] = fmaf(ge, dy2, C5[col]);
           q += d;
           d += dd;
-          dx += 1.f;
         }
-        S0 += R0;
-        S1 += R1;
-        S2 = fmaf(R0, dy, S2);
-        S3 += R3;
-        S4 = fmaf(R1, dy, S4);
-        S5 = fmaf(R0 * dy, dy, S5);
+      }
+      float S0 = 0.f, S1 = 0.f, S2 = 0.f, S3 = 0.f, S4 = 0.f, S5 = 0.f;
+#pragma unroll
+      for (int col = 0; col < kSub; ++col) {
+        const float dx = dx0 + (float)col;
+        S0 += C0[col];
+        const float t1 = C0[col] * dx;
+        S1 += t1;
+        S3 = fmaf(t1, dx, S3);
+        S2 += C2[col];
+        S4 = fmaf(C2[col], dx, S4);
+        S5 += C5[col];
       }
       if (active) {
         s_acc[w][0][e] = S0; s_acc[w][1][e] = S1; s_acc[w][2][e] = S2;
