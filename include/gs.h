@@ -127,8 +127,37 @@ GS_API void gs_plan_destroy(gs_plan *plan);
 
 /* Synchronize the plan's last stream and report the number of Gaussians (or
  * cone-beam (view, Gaussian) pairs) skipped by the last forward call and the
- * number of tile entries it produced.  Either pointer may be NULL. */
+ * number of tile entries it produced (0 for a reserved plan: see
+ * gs_plan_check).  Either pointer may be NULL. */
 GS_API gs_status gs_plan_status(gs_plan *plan, int64_t *skipped, int64_t *tile_entries);
+
+/* Largest problem a reserved plan serves.  Zero counts skip that part. */
+typedef struct {
+  int64_t max_gaussians;     /* Gaussians per projection or voxelization call */
+  int32_t max_views;         /* views per projection call (0: no projection part) */
+  int32_t width, height;     /* detector size of those calls (calls may use smaller) */
+  int64_t max_proj_entries;  /* (view, 16x16 tile, Gaussian) tile-list entries per call */
+  int32_t nx, ny, nz;        /* largest voxel grid (0: no voxelization part) */
+  int64_t max_vox_entries;   /* (8^3 tile, Gaussian) tile-list entries per call */
+  int64_t max_tv_voxels;     /* voxels of the gs_loss_tv blocks (0: none) */
+} gs_reserve;               /* gs_loss_image: stacks up to max_views x height x width */
+
+/* Allocate the plan's whole workspace for problems up to r (synchronizes
+ * `stream`) and switch the plan to reserved mode: from then on projection,
+ * voxelization and loss calls on the plan never allocate and never
+ * synchronize the stream (the binning no longer reads its entry count back),
+ * so a caller can queue many calls ahead of the device or capture them in a
+ * graph.  A call larger than the reservation fails with GS_EINVAL before any
+ * launch.  If a call's tile lists exceed the reserved entries, the device
+ * drops the excess entries (that call's results are incomplete) and records
+ * it; gs_plan_check reports it. */
+GS_API gs_status gs_plan_reserve(gs_plan *plan, const gs_reserve *r, hipStream_t stream);
+
+/* For a reserved plan: synchronize its last stream, report the largest
+ * projection and voxel entry counts any call needed since the previous check
+ * (either pointer may be NULL) and return GS_EOVERFLOW if any call exceeded
+ * the reservation since then.  Clears both records. */
+GS_API gs_status gs_plan_check(gs_plan *plan, int64_t *max_proj_entries, int64_t *max_vox_entries);
 
 /* (host) Fill a cone-beam view for gantry angle theta (radians) as in App. A,
  * Eq. 10: W rows (-sin t, cos t, 0), (0, 0, -1), (-cos t, -sin t, 0); square

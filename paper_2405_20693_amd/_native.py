@@ -56,6 +56,13 @@ class GsRequestResult(ctypes.Structure):
                 ("batch_size", c_int32), ("status", c_int32)]
 
 
+class GsReserve(ctypes.Structure):
+    _fields_ = [("max_gaussians", c_int64), ("max_views", c_int32), ("width", c_int32),
+                ("height", c_int32), ("max_proj_entries", c_int64), ("nx", c_int32),
+                ("ny", c_int32), ("nz", c_int32), ("max_vox_entries", c_int64),
+                ("max_tv_voxels", c_int64)]
+
+
 class GsGradStats(ctypes.Structure):
     _fields_ = [("grad_sum", c_void_p), ("visible", c_void_p), ("scale", c_float)]
 
@@ -119,6 +126,8 @@ EXPORTS = {
     "gs_loss_tv": (ctypes.c_int, [c_void_p, c_int32, c_int32, c_int32, c_float, c_void_p, c_void_p,
                                   c_int32, c_void_p, c_void_p]),
     "gs_plan_set_timing": (ctypes.c_int, [c_void_p, c_int32]),
+    "gs_plan_reserve": (ctypes.c_int, [c_void_p, ctypes.POINTER(GsReserve), c_void_p]),
+    "gs_plan_check": (ctypes.c_int, [c_void_p, ctypes.POINTER(c_int64), ctypes.POINTER(c_int64)]),
     "gs_plan_set_rectify": (ctypes.c_int, [c_void_p, c_int32]),
     "gs_project_mean_mu": (ctypes.c_int, [ctypes.POINTER(GsGaussians), ctypes.POINTER(GsView),
                                           c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
@@ -136,6 +145,8 @@ EXPORTS = {
                                             c_int32, c_float, c_void_p, ctypes.POINTER(GsGrads),
                                             c_int32, ctypes.POINTER(GsGradStats), c_void_p,
                                             c_void_p]),
+    "gs_random_normals": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64, c_int64, c_void_p,
+                                         c_void_p]),
     "gs_adam_step": (ctypes.c_int, [ctypes.POINTER(GsParams), c_int64, ctypes.POINTER(GsGrads),
                                     ctypes.POINTER(GsAdamConfig), c_void_p]),
     "gs_params_activate": (ctypes.c_int, [ctypes.POINTER(GsParams), c_int64, c_void_p]),

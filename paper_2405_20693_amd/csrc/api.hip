@@ -64,13 +64,21 @@ struct gs_plan {
   Buf l_coef, l_part;
   // adaptive control and metrics
   Buf d_action, d_count, d_offsets, d_scan_tmp, d_totals, m_sse, m_max, m_out, m_stack, m_loss;
-  Buf skipped;  // unsigned long long [4]: running projection, voxelization; last call's two
-  // host side
-  gs_view *stage = nullptr;          // pinned staging of per-view constants
-  size_t stage_cap = 0;
+  Buf skipped;  // control words, unsigned long long [8] (layout in internal.h)
+  // host side: a ring of pinned staging buffers for per-view constants, so
+  // that an upload waits only for the copy issued kStageRing uploads earlier
+  static constexpr int kStageRing = 4;
+  void *stage[kStageRing] = {};
+  size_t stage_cap[kStageRing] = {};
+  hipEvent_t stage_done[kStageRing] = {};
+  bool stage_pending[kStageRing] = {};
+  int stage_next = 0;
+  std::vector<gs_view> up_views;     // the views p_views holds
+  bool up_valid = false;
   unsigned long long *readback = nullptr;  // pinned, 4 entries
-  hipEvent_t stage_done = nullptr;
-  bool stage_pending = false;
+  // reserved mode: no allocation and no synchronization in the operator calls
+  bool reserved = false;
+  gs_reserve res{};
   // saved forward state
   bool p_valid = false, v_valid = false;
   ProjKey pkey;
@@ -150,6 +158,7 @@ void release(gs_plan *pl, Buf &b) {
 gs_status ensure(gs_plan *pl, Buf &b, size_t bytes, hipStream_t s) {
   if (bytes == 0) bytes = 256;
   if (b.cap >= bytes) return GS_OK;
+  if (pl->reserved) return fail(GS_EINVAL, "the call exceeds the plan's reservation");
   if (b.p) {
     gs_status st = sync_stream(pl, s);
     if (st != GS_OK) return st;
@@ -176,8 +185,8 @@ gs_status ensure(gs_plan *pl, Buf &b, size_t bytes, hipStream_t s) {
 // fill is needed per call.  All four start at zero.
 gs_status ensure_skipped(gs_plan *pl, hipStream_t s) {
   if (pl->skipped.p) return GS_OK;
-  GS_TRY(ensure(pl, pl->skipped, 32, s));
-  if (hipMemsetAsync(pl->skipped.p, 0, 32, s) != hipSuccess) return fail(GS_EHIP, "hipMemsetAsync");
+  GS_TRY(ensure(pl, pl->skipped, 64, s));
+  if (hipMemsetAsync(pl->skipped.p, 0, 64, s) != hipSuccess) return fail(GS_EHIP, "hipMemsetAsync");
   return GS_OK;
 }
 
@@ -276,28 +285,41 @@ void cutoff_consts(float cutoff, float &kappa, float &thr, float &qmax) {
   }
 }
 
-// Uploads per-view constants through the pinned staging buffer.
+// Uploads per-view constants through the pinned staging ring, unless p_views
+// already holds exactly these views.
 gs_status upload_views(gs_plan *pl, const gs_view *views, int32_t nv, hipStream_t s) {
   size_t bytes = sizeof(DevView) * (size_t)nv;
+  void *before = pl->p_views.p;
   GS_TRY(ensure(pl, pl->p_views, bytes, s));
-  if (pl->stage_pending) {
-    if (hipEventSynchronize(pl->stage_done) != hipSuccess) return fail(GS_EHIP, "hipEventSynchronize");
-    pl->stage_pending = false;
+  if (pl->p_views.p != before) pl->up_valid = false;
+  if (pl->up_valid && pl->up_views.size() == (size_t)nv &&
+      std::memcmp(pl->up_views.data(), views, sizeof(gs_view) * (size_t)nv) == 0)
+    return GS_OK;
+  const int k = pl->stage_next;
+  pl->stage_next = (k + 1) % gs_plan::kStageRing;
+  if (pl->stage_pending[k]) {
+    if (hipEventSynchronize(pl->stage_done[k]) != hipSuccess)
+      return fail(GS_EHIP, "hipEventSynchronize");
+    pl->stage_pending[k] = false;
   }
-  if (pl->stage_cap < bytes) {
-    if (pl->stage) (void)hipHostFree(pl->stage);
-    pl->stage = nullptr;
-    pl->stage_cap = 0;
-    if (hipHostMalloc((void **)&pl->stage, bytes, hipHostMallocDefault) != hipSuccess)
+  if (pl->stage_cap[k] < bytes) {
+    if (pl->reserved) return fail(GS_EINVAL, "the call exceeds the plan's reservation");
+    if (pl->stage[k]) (void)hipHostFree(pl->stage[k]);
+    pl->stage[k] = nullptr;
+    pl->stage_cap[k] = 0;
+    if (hipHostMalloc(&pl->stage[k], bytes, hipHostMallocDefault) != hipSuccess)
       return fail(GS_ENOMEM, "pinned staging allocation failed");
-    pl->stage_cap = bytes;
+    pl->stage_cap[k] = bytes;
   }
-  DevView *dv = reinterpret_cast<DevView *>(pl->stage);
+  DevView *dv = reinterpret_cast<DevView *>(pl->stage[k]);
   for (int i = 0; i < nv; ++i) dv[i] = make_dev_view(views[i]);
-  if (hipMemcpyAsync(pl->p_views.p, pl->stage, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+  pl->up_valid = false;
+  if (hipMemcpyAsync(pl->p_views.p, pl->stage[k], bytes, hipMemcpyHostToDevice, s) != hipSuccess)
     return fail(GS_EHIP, "view upload failed");
-  if (hipEventRecord(pl->stage_done, s) != hipSuccess) return fail(GS_EHIP, "hipEventRecord");
-  pl->stage_pending = true;
+  if (hipEventRecord(pl->stage_done[k], s) != hipSuccess) return fail(GS_EHIP, "hipEventRecord");
+  pl->stage_pending[k] = true;
+  pl->up_views.assign(views, views + nv);
+  pl->up_valid = true;
   return GS_OK;
 }
 
@@ -380,29 +402,36 @@ gs_status proj_bin(gs_plan *pl, const gs_gaussians *g, const gs_view *views, int
   }
   t_bin.stop();
   GS_TRY(check_launch("projection binning"));
-  if (hipMemcpyAsync(pl->readback, pl->p_totals.p, 16, hipMemcpyDeviceToHost, s) != hipSuccess)
-    return fail(GS_EHIP, "entry count readback failed");
-  GS_TRY(sync_stream(pl, s));
-  const unsigned long long entries = pl->readback[0];
-  if (entries != pl->readback[1]) {
-    (void)clear_running_skipped(pl, 0, s);
-    return fail(GS_EHIP, "internal error: tile and Gaussian entry totals differ");
-  }
-  if (entries >= 0xffffffffull) {
-    (void)clear_running_skipped(pl, 0, s);
-    return fail(GS_EOVERFLOW, "more than 2^32-1 tile entries: split the views over several calls");
-  }
-  {
+  unsigned long long entries;
+  if (pl->reserved) {
+    // no readback: the scatter keeps what the reserved list and slots hold
+    entries = std::min(pl->p_list.cap / 8, pl->p_slots.cap / 24);
+    entries = std::min<unsigned long long>(entries, 0xffffffffull);
+  } else {
+    if (hipMemcpyAsync(pl->readback, pl->p_totals.p, 16, hipMemcpyDeviceToHost, s) != hipSuccess)
+      return fail(GS_EHIP, "entry count readback failed");
+    GS_TRY(sync_stream(pl, s));
+    entries = pl->readback[0];
+    if (entries != pl->readback[1]) {
+      (void)clear_running_skipped(pl, 0, s);
+      return fail(GS_EHIP, "internal error: tile and Gaussian entry totals differ");
+    }
+    if (entries >= 0xffffffffull) {
+      (void)clear_running_skipped(pl, 0, s);
+      return fail(GS_EOVERFLOW, "more than 2^32-1 tile entries: split the views over several calls");
+    }
     gs_status st = ensure(pl, pl->p_list, 8 * (size_t)entries, s);
     if (st != GS_OK) {
       (void)clear_running_skipped(pl, 0, s);
       return st;
     }
   }
+  a.cap = (uint32_t)entries;
   StageTimer t_sc(pl, GS_STAGE_PROJ_SCATTER, s);
   launch_proj_scatter(a, P<Rec2>(pl->p_rec), P<uint32_t>(pl->p_hist), P<uint32_t>(pl->p_tile_start),
                       P<uint32_t>(pl->p_chunk_start), P<uint2>(pl->p_list),
-                      P<uint32_t>(pl->p_offsets), P<unsigned long long>(pl->skipped), s);
+                      P<uint32_t>(pl->p_offsets), P<unsigned long long>(pl->skipped),
+                      P<unsigned long long>(pl->p_totals), s);
   t_sc.stop();
   GS_TRY(check_launch("projection scatter"));
   pl->pargs = a;
@@ -467,28 +496,34 @@ gs_status vox_bin(gs_plan *pl, const gs_gaussians *g, const gs_grid *grid, float
                nullptr, 0, P<unsigned long long>(pl->v_totals), s);
   t_bin.stop();
   GS_TRY(check_launch("voxel binning"));
-  if (hipMemcpyAsync(pl->readback, pl->v_totals.p, 16, hipMemcpyDeviceToHost, s) != hipSuccess)
-    return fail(GS_EHIP, "entry count readback failed");
-  GS_TRY(sync_stream(pl, s));
-  const unsigned long long entries = pl->readback[0];
-  if (entries != pl->readback[1]) {
-    (void)clear_running_skipped(pl, 1, s);
-    return fail(GS_EHIP, "internal error: tile and Gaussian entry totals differ");
-  }
-  if (entries >= 0xffffffffull) {
-    (void)clear_running_skipped(pl, 1, s);
-    return fail(GS_EOVERFLOW, "more than 2^32-1 voxel tile entries");
-  }
-  {
+  unsigned long long entries;
+  if (pl->reserved) {
+    entries = std::min(pl->v_list.cap / 4, pl->v_slots.cap / 40);
+    entries = std::min<unsigned long long>(entries, 0xffffffffull);
+  } else {
+    if (hipMemcpyAsync(pl->readback, pl->v_totals.p, 16, hipMemcpyDeviceToHost, s) != hipSuccess)
+      return fail(GS_EHIP, "entry count readback failed");
+    GS_TRY(sync_stream(pl, s));
+    entries = pl->readback[0];
+    if (entries != pl->readback[1]) {
+      (void)clear_running_skipped(pl, 1, s);
+      return fail(GS_EHIP, "internal error: tile and Gaussian entry totals differ");
+    }
+    if (entries >= 0xffffffffull) {
+      (void)clear_running_skipped(pl, 1, s);
+      return fail(GS_EOVERFLOW, "more than 2^32-1 voxel tile entries");
+    }
     gs_status st = ensure(pl, pl->v_list, 4 * (size_t)entries, s);
     if (st != GS_OK) {
       (void)clear_running_skipped(pl, 1, s);
       return st;
     }
   }
+  a.cap = (uint32_t)entries;
   StageTimer t_sc(pl, GS_STAGE_VOX_SCATTER, s);
   launch_vox_scatter(a, P<Rec3>(pl->v_rec), P<uint32_t>(pl->v_hist), P<uint32_t>(pl->v_tile_start),
-                     P<uint32_t>(pl->v_list), P<unsigned long long>(pl->skipped), s);
+                     P<uint32_t>(pl->v_list), P<unsigned long long>(pl->skipped),
+                     P<unsigned long long>(pl->v_totals), s);
   t_sc.stop();
   GS_TRY(check_launch("voxel scatter"));
   pl->vargs = a;
@@ -533,11 +568,13 @@ gs_status gs_plan_create(gs_alloc_fn alloc, gs_free_fn free_fn, void *ctx, gs_pl
     delete p;
     return fail(GS_EHIP, "pinned readback allocation failed");
   }
-  if (hipEventCreateWithFlags(&p->stage_done, hipEventDisableTiming) != hipSuccess) {
-    (void)hipHostFree(p->readback);
-    delete p;
-    return fail(GS_EHIP, "hipEventCreate failed");
-  }
+  for (int k = 0; k < gs_plan::kStageRing; ++k)
+    if (hipEventCreateWithFlags(&p->stage_done[k], hipEventDisableTiming) != hipSuccess) {
+      for (int j = 0; j < k; ++j) (void)hipEventDestroy(p->stage_done[j]);
+      (void)hipHostFree(p->readback);
+      delete p;
+      return fail(GS_EHIP, "hipEventCreate failed");
+    }
   *out = p;
   return GS_OK;
 }
@@ -555,9 +592,11 @@ void gs_plan_destroy(gs_plan *p) {
                  &p->d_scan_tmp, &p->d_totals, &p->m_sse, &p->m_max, &p->m_out, &p->m_stack,
                  &p->m_loss};
   for (Buf *b : bufs) release(p, *b);
-  if (p->stage) (void)hipHostFree(p->stage);
+  for (int k = 0; k < gs_plan::kStageRing; ++k) {
+    if (p->stage[k]) (void)hipHostFree(p->stage[k]);
+    if (p->stage_done[k]) (void)hipEventDestroy(p->stage_done[k]);
+  }
   if (p->readback) (void)hipHostFree(p->readback);
-  if (p->stage_done) (void)hipEventDestroy(p->stage_done);
   for (auto &t : p->timed) {
     (void)hipEventDestroy(t.a);
     (void)hipEventDestroy(t.b);
@@ -569,14 +608,122 @@ void gs_plan_destroy(gs_plan *p) {
 gs_status gs_plan_status(gs_plan *p, int64_t *skipped, int64_t *tile_entries) {
   if (!p) return fail(GS_EINVAL, "plan is NULL");
   if (skipped) *skipped = 0;
-  if (tile_entries) *tile_entries = (int64_t)(p->p_valid ? p->p_entries : 0) +
-                                    (int64_t)(p->v_valid ? p->v_entries : 0);
+  if (tile_entries && !p->reserved)
+    *tile_entries = (int64_t)(p->p_valid ? p->p_entries : 0) +
+                    (int64_t)(p->v_valid ? p->v_entries : 0);
+  else if (tile_entries)
+    *tile_entries = 0;
   if (!p->used || !p->skipped.p) return GS_OK;
   GS_TRY(sync_stream(p, p->last_stream));
   unsigned long long h[4] = {0, 0, 0, 0};
   if (hipMemcpy(h, p->skipped.p, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
     return fail(GS_EHIP, "status readback failed");
   if (skipped) *skipped = (int64_t)(h[2] + h[3]);
+  return GS_OK;
+}
+
+gs_status gs_plan_reserve(gs_plan *p, const gs_reserve *r, hipStream_t s) {
+  if (!p || !r) return fail(GS_EINVAL, "plan or reservation is NULL");
+  if (r->max_gaussians < 0 || r->max_gaussians > 0x7fffffffLL || r->max_views < 0 ||
+      r->max_proj_entries < 0 || r->max_proj_entries >= 0xffffffffLL || r->max_vox_entries < 0 ||
+      r->max_vox_entries >= 0xffffffffLL || r->max_tv_voxels < 0 ||
+      (r->max_views > 0 && (r->width < 1 || r->height < 1 || r->width > 16384 || r->height > 16384)) ||
+      (r->nx < 0 || r->ny < 0 || r->nz < 0 || r->nx > 16384 || r->ny > 16384 || r->nz > 16384))
+    return fail(GS_EINVAL, "reservation sizes out of range");
+  p->reserved = false;  // allocate first
+  p->used = true;
+  p->last_stream = s;
+  const int64_t M = std::max<int64_t>(r->max_gaussians, 1);
+  const int64_t Cmax16 = (M + 4095) / 4096;  // chunks at the largest chunk size
+  GS_TRY(ensure_skipped(p, s));
+  if (r->max_views > 0) {
+    const int64_t V = r->max_views;
+    const int64_t T = (int64_t)((r->width + kTile - 1) / kTile) * ((r->height + kTile - 1) / kTile);
+    if (T > kMaxTilesPerGroup) return fail(GS_EUNSUPPORTED, "detector has more than 16384 tiles");
+    // binning chunks shrink only while views x chunks < 512, so views x chunks
+    // stays below max(V ceil(M / 4096), 1024 + V) for any M' <= M and V' <= V
+    const int64_t VC = std::max<int64_t>(V * Cmax16, 1024 + V);
+    const int64_t VT = V * T, E = r->max_proj_entries;
+    GS_TRY(ensure(p, p->p_views, sizeof(DevView) * V, s));
+    GS_TRY(ensure(p, p->p_rec, sizeof(Rec2) * V * M, s));
+    GS_TRY(ensure(p, p->p_hist, 4 * VC * T, s));
+    GS_TRY(ensure(p, p->p_tile_total, 4 * VT, s));
+    GS_TRY(ensure(p, p->p_tile_start, 4 * (VT + 1), s));
+    GS_TRY(ensure(p, p->p_chunk_cnt, 4 * VC, s));
+    GS_TRY(ensure(p, p->p_chunk_start, 4 * (VC + 1), s));
+    GS_TRY(ensure(p, p->p_offsets, 4 * V * M, s));
+    GS_TRY(ensure(p, p->p_totals, 16, s));
+    GS_TRY(ensure(p, p->p_scan_tmp, 4 * (size_t)(2 * ((VT + 4095) / 4096) + 2 * ((VC + 4095) / 4096) + 2), s));
+    GS_TRY(ensure(p, p->p_list, 8 * (size_t)std::max<int64_t>(E, 1), s));
+    GS_TRY(ensure(p, p->p_slots, 24 * (size_t)std::max<int64_t>(E, 1), s));
+    GS_TRY(ensure(p, p->p_part, 72 * (size_t)proj_chain_chunks((int)V) * (size_t)M, s));
+    // render parts x tiles stays below 8192 + tiles
+    GS_TRY(ensure(p, p->p_fpart, 4 * (size_t)kBlock * (size_t)(8192 + VT), s));
+    GS_TRY(ensure(p, p->l_coef, 12 * (size_t)V * r->width * r->height, s));
+    GS_TRY(ensure(p, p->l_part, 8 * (size_t)ssim_num_blocks((int)V, r->height, r->width), s));
+    for (int k = 0; k < gs_plan::kStageRing; ++k) {
+      const size_t bytes = sizeof(DevView) * (size_t)V;
+      if (p->stage_cap[k] < bytes) {
+        if (p->stage_pending[k] && hipEventSynchronize(p->stage_done[k]) != hipSuccess)
+          return fail(GS_EHIP, "hipEventSynchronize");
+        p->stage_pending[k] = false;
+        if (p->stage[k]) (void)hipHostFree(p->stage[k]);
+        p->stage[k] = nullptr;
+        p->stage_cap[k] = 0;
+        if (hipHostMalloc(&p->stage[k], bytes, hipHostMallocDefault) != hipSuccess)
+          return fail(GS_ENOMEM, "pinned staging allocation failed");
+        p->stage_cap[k] = bytes;
+      }
+    }
+  }
+  if (r->nx > 0 && r->ny > 0 && r->nz > 0) {
+    const int64_t TX = (r->nx + kVTile - 1) / kVTile, TY = (r->ny + kVTile - 1) / kVTile,
+                  TZ = (r->nz + kVTile - 1) / kVTile;
+    if (TX * TY > kMaxTilesPerGroup) return fail(GS_EUNSUPPORTED, "grid plane has more than 16384 tiles");
+    // a group holds max(1, 4096 / plane) tile planes, so tiles per group <=
+    // max(4096, plane) and groups x tiles per group <= tiles + that; groups
+    // x chunks as for the projection
+    const int64_t Tg = std::max<int64_t>(4096, TX * TY), GT = TX * TY * TZ + Tg, G = TZ;
+    const int64_t GC = std::max<int64_t>(G * Cmax16, 1024 + G);
+    const int64_t E = r->max_vox_entries, nb = (M + 4095) / 4096 + 1;
+    GS_TRY(ensure(p, p->v_rec, sizeof(Rec3) * (size_t)M, s));
+    GS_TRY(ensure(p, p->v_count, 4 * (size_t)M, s));
+    GS_TRY(ensure(p, p->v_offsets, 4 * (size_t)(M + 1), s));
+    GS_TRY(ensure(p, p->v_scan_tmp, 4 * (size_t)(2 * nb + 1), s));
+    GS_TRY(ensure(p, p->v_hist, 4 * (size_t)(GC * Tg), s));
+    GS_TRY(ensure(p, p->v_tile_total, 4 * (size_t)GT, s));
+    GS_TRY(ensure(p, p->v_tile_start, 4 * (size_t)(GT + 1), s));
+    GS_TRY(ensure(p, p->v_totals, 16, s));
+    GS_TRY(ensure(p, p->v_list, 4 * (size_t)std::max<int64_t>(E, 1), s));
+    GS_TRY(ensure(p, p->v_slots, 40 * (size_t)std::max<int64_t>(E, 1), s));
+    GS_TRY(ensure(p, p->v_fpart, 4 * 2 * (size_t)kBlock * (size_t)(4096 + GT), s));  // parts x tiles
+  }
+  if (r->max_tv_voxels > 0) {
+    const size_t nb = (size_t)((r->max_tv_voxels + kBlock - 1) / kBlock);
+    GS_TRY(ensure(p, p->l_part, 4 * nb, s));
+  }
+  GS_TRY(sync_stream(p, s));
+  p->res = *r;
+  p->reserved = true;
+  return GS_OK;
+}
+
+gs_status gs_plan_check(gs_plan *p, int64_t *max_proj_entries, int64_t *max_vox_entries) {
+  if (!p) return fail(GS_EINVAL, "plan is NULL");
+  if (max_proj_entries) *max_proj_entries = 0;
+  if (max_vox_entries) *max_vox_entries = 0;
+  if (!p->skipped.p) return GS_OK;
+  if (p->used) GS_TRY(sync_stream(p, p->last_stream));
+  unsigned long long h[8];
+  if (hipMemcpy(h, p->skipped.p, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(GS_EHIP, "check readback failed");
+  if (max_proj_entries) *max_proj_entries = (int64_t)h[4];
+  if (max_vox_entries) *max_vox_entries = (int64_t)h[5];
+  if (hipMemset(reinterpret_cast<unsigned long long *>(p->skipped.p) + 4, 0, 32) != hipSuccess)
+    return fail(GS_EHIP, "check reset failed");
+  if (h[6] || h[7])
+    return fail(GS_EOVERFLOW, std::to_string(h[6] + h[7]) +
+                                  " call(s) needed more tile entries than reserved");
   return GS_OK;
 }
 
@@ -913,6 +1060,15 @@ gs_status gs_adam_step(const gs_params *p, int64_t n, const gs_grads *grads,
   a.bc2_inv = (float)(1.0 / (1.0 - std::pow(b2, cfg->step)));
   launch_adam(a, stream);
   return check_launch("adam step");
+}
+
+gs_status gs_random_normals(uint64_t seed, uint64_t counter, int64_t n, float *out,
+                            hipStream_t stream) {
+  if (n < 0 || (n > 0 && !out)) return fail(GS_EINVAL, "n < 0 or out is NULL");
+  if (n > ((int64_t)1 << 34)) return fail(GS_EINVAL, "more than 2^34 draws in one call");
+  if (n == 0) return GS_OK;
+  launch_random_normals(seed, counter, n, out, stream);
+  return check_launch("random normals");
 }
 
 gs_status gs_params_activate(const gs_params *p, int64_t n, hipStream_t stream) {

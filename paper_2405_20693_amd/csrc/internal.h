@@ -279,6 +279,7 @@ struct ProjArgs {
   int rectify;                    // 1: rho_hat = mu rho (Eq. 7); 0: rho_hat = rho (unrectified)
   int cpt;                        // Gaussians per thread per binning chunk (chunk = kBlock * cpt)
   int parts;                      // workgroups per tile list in the render kernels (>= 1)
+  uint32_t cap;                   // tile-list entries the list and slot buffers hold
 };
 
 void launch_mean_mu(const ProjArgs &a, float *mu_out, float *density_out, hipStream_t s);
@@ -289,11 +290,16 @@ void launch_hist_colscan(int groups, int C, int T, uint32_t *hist, uint32_t *til
 void launch_scan2(const uint32_t *in0, uint32_t *out0, int n0, const uint32_t *in1, uint32_t *out1,
                   int n1, unsigned long long *totals, hipStream_t s);
 // Tile-list entries are (Gaussian index, backward slot) pairs.
-// skipped [4]: the scatter moves the running projection count (0) to the
-// last-call slot (2) and clears it.
+// Control words of a plan (unsigned long long [8]): 0, 1 running skipped
+// counts of the projection and voxelization binning; 2, 3 the last call's;
+// 4, 5 the largest entry count since the last check; 6, 7 the number of calls
+// whose entries exceeded the capacity since then.  The projection scatter
+// moves 0 to 2, clears 0 and records 4 and 6 from totals[0]; entries at
+// positions >= a.cap are dropped.
 void launch_proj_scatter(const ProjArgs &a, const Rec2 *rec, const uint32_t *hist,
                          const uint32_t *tile_start, const uint32_t *chunk_start, uint2 *list,
-                         uint32_t *offsets, unsigned long long *skipped, hipStream_t s);
+                         uint32_t *offsets, unsigned long long *ctl,
+                         const unsigned long long *totals, hipStream_t s);
 // With a.parts > 1, each part of a tile list writes its pixel sums to
 // partial [parts][V * T][256] and a second kernel adds the parts in order.
 void launch_render_fwd(const ProjArgs &a, const Rec2 *rec, const uint2 *list,
@@ -330,6 +336,7 @@ struct VoxArgs {
   int cpt;                 // Gaussians per thread per binning chunk (chunk = kBlock * cpt)
   int parts;               // workgroups per tile list in the forward (>= 1)
   int bparts;              // and in the backward (its per-batch setup favours fewer parts)
+  uint32_t cap;            // tile-list entries the list and slot buffers hold
 };
 
 void launch_vox_records(const VoxArgs &a, Rec3 *rec, uint32_t *count,
@@ -337,10 +344,11 @@ void launch_vox_records(const VoxArgs &a, Rec3 *rec, uint32_t *count,
 void launch_scan_big(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *block_tmp,
                      unsigned long long *total, hipStream_t s);
 void launch_vox_hist(const VoxArgs &a, const Rec3 *rec, uint32_t *hist, hipStream_t s);
-// skipped [4]: moves the running voxelization count (1) to slot 3, clears it.
+// Control words as for the projection: moves 1 to 3, clears 1, records 5
+// and 7 from totals[0]; entries at positions >= a.cap are dropped.
 void launch_vox_scatter(const VoxArgs &a, const Rec3 *rec, const uint32_t *hist,
-                        const uint32_t *tile_start, uint32_t *list, unsigned long long *skipped,
-                        hipStream_t s);
+                        const uint32_t *tile_start, uint32_t *list, unsigned long long *ctl,
+                        const unsigned long long *totals, hipStream_t s);
 // With a.parts > 1, partial [parts][G * Tg][512] holds each part's voxel sums,
 // added in part order by a second kernel.
 void launch_vox_fwd(const VoxArgs &a, const Rec3 *rec, const uint32_t *list,
@@ -380,6 +388,7 @@ struct AdamArgs {
   float eps, bc1_inv, bc2_inv;
 };
 void launch_adam(const AdamArgs &a, hipStream_t s);
+void launch_random_normals(uint64_t seed, uint64_t counter, int64_t n, float *out, hipStream_t s);
 void launch_activate(float *log_scale, float *density_raw, float *scale, float *density, int64_t n,
                      int inverse, hipStream_t s);
 

@@ -198,13 +198,17 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
                                                          const uint32_t *__restrict__ chunk_start,
                                                          uint2 *__restrict__ list,
                                                          uint32_t *__restrict__ offsets,
-                                                         unsigned long long *skipped) {
+                                                         unsigned long long *ctl,
+                                                         const unsigned long long *totals) {
   extern __shared__ uint32_t cur[];
   __shared__ uint32_t sh4[4];
   const int c = blockIdx.x, v = blockIdx.y, tid = threadIdx.x;
-  if (c == 0 && v == 0 && tid == 0) {  // the binning kernel of this call has finished
-    skipped[2] = skipped[0];
-    skipped[0] = 0ull;
+  if (c == 0 && v == 0 && tid == 0) {  // the binning kernels of this call have finished
+    ctl[2] = ctl[0];
+    ctl[0] = 0ull;
+    const unsigned long long e = totals[0];
+    atomicMax(&ctl[4], e);
+    if (e > a.cap) atomicAdd(&ctl[6], 1ull);
   }
   const uint32_t *h = hist + ((int64_t)v * a.C + c) * a.T;
   const uint32_t *ts = tile_start + (int64_t)v * a.T;
@@ -230,7 +234,8 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
     for (int ty = rc.y0; ty <= rc.y1 && n; ++ty)
       for (int tx = rc.x0; tx <= rc.x1; ++tx) {
         uint32_t pos = atomicAdd(&cur[ty * a.TX + tx], 1u);
-        list[pos] = make_uint2((uint32_t)g, slot++);
+        if (pos < a.cap) list[pos] = make_uint2((uint32_t)g, slot);
+        ++slot;
       }
     base += total;
   }
@@ -238,10 +243,11 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
 
 void launch_proj_scatter(const ProjArgs &a, const Rec2 *rec, const uint32_t *hist,
                          const uint32_t *tile_start, const uint32_t *chunk_start, uint2 *list,
-                         uint32_t *offsets, unsigned long long *skipped, hipStream_t s) {
+                         uint32_t *offsets, unsigned long long *ctl,
+                         const unsigned long long *totals, hipStream_t s) {
   dim3 grid(a.C, a.V);
   hipLaunchKernelGGL(k_proj_scatter, grid, dim3(kBlock), a.T * sizeof(uint32_t), s, a, rec, hist,
-                     tile_start, chunk_start, list, offsets, skipped);
+                     tile_start, chunk_start, list, offsets, ctl, totals);
 }
 
 // ------------------------------------------------------- render forward --
@@ -276,7 +282,8 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
   const float lxx = lx * lx, lxy = lx * ly, lyy = ly * ly;
   const float hs = 0.5f * (kSub - 1);
   uint32_t beg, end;
-  list_part(tile_start[item], tile_start[item + 1], part, a.parts, beg, end);
+  list_part(min(tile_start[item], a.cap), min(tile_start[item + 1], a.cap), part, a.parts, beg,
+            end);
   const Rec2 *rv = rec + (int64_t)v * a.M;
   const float thr = a.thr;
   float acc0 = 0.f, acc1 = 0.f;
@@ -420,7 +427,8 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *_
                    : 0.f;
   }
   uint32_t beg, end;
-  list_part(tile_start[item], tile_start[item + 1], part, a.parts, beg, end);
+  list_part(min(tile_start[item], a.cap), min(tile_start[item + 1], a.cap), part, a.parts, beg,
+            end);
   const Rec2 *rv = rec + (int64_t)v * a.M;
   for (uint32_t base = beg; base < end; base += kBlock) {
     const int n = (int)min((uint32_t)kBlock, end - base);
@@ -511,7 +519,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *_
       }
     }
     __syncthreads();
-    if (tid < n) {
+    if (tid < n && my_slot < a.cap) {
       float *o = slots + (int64_t)my_slot * 6;
 #pragma unroll
       for (int k = 0; k < 6; ++k)
@@ -561,8 +569,9 @@ __global__ __launch_bounds__(kBlock) void k_proj_chain(ProjArgs a, const Rec2 *_
       const Rec2 r = rec[vg];
       const Rect2 rc = unpack_rect(r.r0, r.r1);
       const int cnt = rect_count(rc);
-      if (!cnt) continue;
-      const float *sl = slots + (int64_t)offsets[vg] * 6;
+      const uint32_t off = offsets[vg];
+      if (!cnt || (uint64_t)off + (uint64_t)cnt > a.cap) continue;  // (beyond capacity: dropped)
+      const float *sl = slots + (int64_t)off * 6;
       float S[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       for (int k = 0; k < cnt; ++k)
 #pragma unroll

@@ -115,12 +115,16 @@ __global__ __launch_bounds__(kBlock) void k_vox_scatter(VoxArgs a, const Rec3 *_
                                                         const uint32_t *__restrict__ hist,
                                                         const uint32_t *__restrict__ tile_start,
                                                         uint32_t *__restrict__ list,
-                                                        unsigned long long *skipped) {
+                                                        unsigned long long *ctl,
+                                                        const unsigned long long *totals) {
   extern __shared__ uint32_t cur[];
   const int c = blockIdx.x, grp = blockIdx.y, tid = threadIdx.x;
-  if (c == 0 && grp == 0 && tid == 0) {  // the record kernel of this call has finished
-    skipped[3] = skipped[1];
-    skipped[1] = 0ull;
+  if (c == 0 && grp == 0 && tid == 0) {  // the binning kernels of this call have finished
+    ctl[3] = ctl[1];
+    ctl[1] = 0ull;
+    const unsigned long long e = totals[0];
+    atomicMax(&ctl[5], e);
+    if (e > a.cap) atomicAdd(&ctl[7], 1ull);
   }
   const uint32_t *hp = hist + ((int64_t)grp * a.C + c) * a.Tg;
   const uint32_t *ts = tile_start + (int64_t)grp * a.Tg;
@@ -138,16 +142,16 @@ __global__ __launch_bounds__(kBlock) void k_vox_scatter(VoxArgs a, const Rec3 *_
       for (int ty = b.y0; ty <= b.y1; ++ty)
         for (int tx = b.x0; tx <= b.x1; ++tx) {
           uint32_t pos = atomicAdd(&cur[group_tile(a, grp, tx, ty, tz)], 1u);
-          list[pos] = (uint32_t)g;
+          if (pos < a.cap) list[pos] = (uint32_t)g;
         }
   }
 }
 
 void launch_vox_scatter(const VoxArgs &a, const Rec3 *rec, const uint32_t *hist,
-                        const uint32_t *tile_start, uint32_t *list, unsigned long long *skipped,
-                        hipStream_t s) {
+                        const uint32_t *tile_start, uint32_t *list, unsigned long long *ctl,
+                        const unsigned long long *totals, hipStream_t s) {
   hipLaunchKernelGGL(k_vox_scatter, dim3(a.C, a.G), dim3(kBlock), a.Tg * sizeof(uint32_t), s, a,
-                     rec, hist, tile_start, list, skipped);
+                     rec, hist, tile_start, list, ctl, totals);
 }
 
 // --------------------------------------------------------------- forward --
@@ -217,7 +221,8 @@ __global__ __launch_bounds__(kBlock) void k_vox_fwd(VoxArgs a, const Rec3 *__res
     vz[k] = (int)oz[k] + (lane >> 4);
   }
   uint32_t beg, end;
-  list_part(tile_start[item], tile_start[item + 1], part, a.parts, beg, end);
+  list_part(min(tile_start[item], a.cap), min(tile_start[item + 1], a.cap), part, a.parts, beg,
+            end);
   for (uint32_t base = beg; base < end; base += kBlock) {
     const int n = (int)min((uint32_t)kBlock, end - base);
     __syncthreads();
@@ -307,7 +312,8 @@ __global__ __launch_bounds__(kBlock) void k_vox_bwd(VoxArgs a, const Rec3 *__res
     s_H[i] = (x < a.nx && y < a.ny && z < a.nz) ? grad_vol[((int64_t)z * a.ny + y) * a.nx + x] : 0.f;
   }
   uint32_t beg, end;
-  list_part(tile_start[item], tile_start[item + 1], part, a.bparts, beg, end);
+  list_part(min(tile_start[item], a.cap), min(tile_start[item + 1], a.cap), part, a.bparts, beg,
+            end);
   for (uint32_t base = beg; base < end; base += kBlock) {
     const int n = (int)min((uint32_t)kBlock, end - base);
     __syncthreads();
@@ -379,7 +385,7 @@ __global__ __launch_bounds__(kBlock) void k_vox_bwd(VoxArgs a, const Rec3 *__res
       }
     }
     __syncthreads();
-    if (tid < n) {
+    if (tid < n && my_slot < a.cap) {
       float *o = slots + (int64_t)my_slot * 10;
       for (int k = 0; k < 10; ++k)
         o[k] = ((s_acc[0][k][tid] + s_acc[1][k][tid]) + s_acc[2][k][tid]) + s_acc[3][k][tid];
@@ -410,10 +416,11 @@ __global__ __launch_bounds__(kBlock) void k_vox_chain(VoxArgs a, const Rec3 *__r
   float grho = 0.f;
   const Rec3 r = rec[g];
   const int cnt = box_count(unpack_box(r));
-  if (G.ok && cnt) {
+  const uint32_t off = offsets[g];
+  if (G.ok && cnt && (uint64_t)off + (uint64_t)cnt <= a.cap) {  // (beyond capacity: dropped)
     float S[10];
     for (int k = 0; k < 10; ++k) S[k] = 0.f;
-    const float *sl = slots + (int64_t)offsets[g] * 10;
+    const float *sl = slots + (int64_t)off * 10;
     for (int i = 0; i < cnt; ++i)
       for (int k = 0; k < 10; ++k) S[k] += sl[10 * i + k];
     const float *h = a.spacing;

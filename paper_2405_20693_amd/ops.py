@@ -50,6 +50,22 @@ class Plan:
         N.call("gs_plan_status", self._h, ctypes.byref(sk), ctypes.byref(en))
         return {"skipped": sk.value, "tile_entries": en.value}
 
+    def reserve(self, max_gaussians, max_views=0, width=0, height=0, max_proj_entries=0,
+                grid=(0, 0, 0), max_vox_entries=0, max_tv_voxels=0):
+        """Allocate for problems up to these sizes and stop allocating and
+        synchronizing in operator calls (gs_plan_reserve)."""
+        r = N.GsReserve(int(max_gaussians), int(max_views), int(width), int(height),
+                        int(max_proj_entries), int(grid[0]), int(grid[1]), int(grid[2]),
+                        int(max_vox_entries), int(max_tv_voxels))
+        N.call("gs_plan_reserve", self._h, ctypes.byref(r), _stream())
+
+    def check(self):
+        """(largest projection entries, largest voxel entries) since the last
+        check; raises GsError (GS_EOVERFLOW) if a call exceeded the reservation."""
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        N.call("gs_plan_check", self._h, ctypes.byref(a), ctypes.byref(b))
+        return a.value, b.value
+
     def set_rectify(self, enable=True):
         """False: unrectified (3DGS-style) projection rho_hat = rho."""
         N.call("gs_plan_set_rectify", self._h, int(bool(enable)))
