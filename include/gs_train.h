@@ -98,6 +98,15 @@ typedef struct {
   int32_t densify;        /* 0: only remove empty Gaussians */
 } gs_densify_config;
 
+/* n standard normal draws into out (device [n]), e.g. the split draws of
+ * gs_densify: Philox4x32-10 (Salmon et al., SC 2011) with counter
+ * (b, counter_lo, counter_hi, 0) and key (seed_lo, seed_hi) gives four words
+ * for elements 4b .. 4b + 3; each word x becomes u = (x + 1/2) 2^-32 and the
+ * pairs (u0, u1), (u2, u3) become sqrt(-2 ln u) (cos 2 pi v, sin 2 pi v)
+ * (Box-Muller), evaluated in double and rounded.  No sync. */
+GS_API gs_status gs_random_normals(uint64_t seed, uint64_t counter, int64_t n, float *out,
+                                   hipStream_t stream);
+
 /* Adaptive density control (Sec. 3.3) from src (n Gaussians) into dst
  * (capacity dst_capacity; dst must not overlap src).  Each source Gaussian
  * writes its 0, 1 or 2 results in source order: kept -> itself (same
@@ -143,7 +152,8 @@ typedef struct {
   float min_density;         /* see gs_densify_config */
   float cutoff;              /* Mahalanobis cutoff (3) */
   int32_t rectify;           /* 1: R^2-Gaussian; 0: the unrectified X-3DGS variant */
-  uint64_t seed;             /* view order, TV blocks and split draws of gs_trainer_run */
+  uint64_t seed;             /* view order and TV blocks of gs_trainer_run (host generator);
+                                split draws: gs_random_normals(seed, iteration index) */
 } gs_train_config;
 
 /* Fills the defaults of Sec. 4.1 (clone_max_scale 0.02, min_density 1e-4 and
@@ -160,8 +170,9 @@ GS_API gs_status gs_trainer_create(const gs_train_config *cfg, const gs_gaussian
                                    const gs_grid *grid, gs_trainer **out);
 GS_API void gs_trainer_destroy(gs_trainer *tr);
 
-/* Runs `iters` iterations drawing views (a reshuffled stack, as 3DGS does),
- * TV block offsets and split normals from the seeded host generator.
+/* Runs `iters` iterations drawing views (a reshuffled stack, as 3DGS does)
+ * and TV block offsets from the seeded host generator, and the split draws of
+ * a densifying iteration k (1-based) as gs_random_normals(seed, k - 1).
  * losses: host [iters] or NULL, receives each iteration's total loss (Eq. 8).
  * Synchronizes at the end only (and at densification steps). */
 GS_API gs_status gs_trainer_run(gs_trainer *tr, int32_t iters, float *losses);

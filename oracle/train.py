@@ -211,3 +211,50 @@ def volume_ssim(vol, gt):
         ys = y.movedim(axis, 0).contiguous()
         vals.append(float(_ssim(xs, ys)))
     return float(np.mean(vals))
+
+
+# ---------------------------------------------------------------------------
+# Split draws: a counter-based generator, so that both implementations draw
+# the same normals without passing them around
+# ---------------------------------------------------------------------------
+
+PHILOX_M = (0xD2511F53, 0xCD9E8D57)
+PHILOX_W = (0x9E3779B9, 0xBB67AE85)
+MASK32 = 0xFFFFFFFF
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, "Parallel random
+    numbers: as easy as 1, 2, 3", SC 2011): each round multiplies words 0 and
+    2 by the two constants, exchanges and xors the 32-bit halves with the
+    other words and the key; the key advances by the Weyl constants between
+    rounds.  ctr: 4 ints, key: 2 ints; returns 4 ints."""
+    c0, c1, c2, c3 = (int(x) & MASK32 for x in ctr)
+    k0, k1 = (int(x) & MASK32 for x in key)
+    for r in range(10):
+        if r:
+            k0 = (k0 + PHILOX_W[0]) & MASK32
+            k1 = (k1 + PHILOX_W[1]) & MASK32
+        p0 = PHILOX_M[0] * c0
+        p1 = PHILOX_M[1] * c2
+        c0, c1, c2, c3 = ((p1 >> 32) ^ c1 ^ k0) & MASK32, p1 & MASK32, \
+                         ((p0 >> 32) ^ c3 ^ k1) & MASK32, p0 & MASK32
+    return c0, c1, c2, c3
+
+
+def random_normals(seed, counter, n):
+    """n standard normal draws: block b gives four words
+    philox4x32_10((b, counter_lo, counter_hi, 0), (seed_lo, seed_hi)); each
+    word x becomes u = (x + 1/2) / 2^32 in (0, 1), and the pairs (u0, u1),
+    (u2, u3) become sqrt(-2 ln u) cos 2 pi v, sqrt(-2 ln u) sin 2 pi v
+    (Box & Muller 1958).  Element 4b + k is the k-th normal of block b."""
+    out = np.zeros(((n + 3) // 4) * 4)
+    key = (seed & MASK32, (seed >> 32) & MASK32)
+    for b in range((n + 3) // 4):
+        x = philox4x32_10((b, counter & MASK32, (counter >> 32) & MASK32, 0), key)
+        u = [(xi + 0.5) / 2.0 ** 32 for xi in x]
+        for j in (0, 2):
+            r = math.sqrt(-2.0 * math.log(u[j]))
+            out[4 * b + j] = r * math.cos(2 * math.pi * u[j + 1])
+            out[4 * b + j + 1] = r * math.sin(2 * math.pi * u[j + 1])
+    return out[:n]

@@ -264,7 +264,51 @@ __global__ __launch_bounds__(kBlock) void k_slices(const float *vol, int nx, int
   }
 }
 
+// Philox4x32-10 (Salmon et al., SC 2011) on counter (b, counter_lo,
+// counter_hi, 0) and key (seed_lo, seed_hi), then Box-Muller on the four
+// words as two pairs; thread b writes normals 4b .. 4b + 3 (in double, then
+// rounded: the draws are few and feed positions).
+__global__ __launch_bounds__(kBlock) void k_random_normals(uint32_t s0, uint32_t s1, uint32_t c1,
+                                                           uint32_t c2, int64_t n,
+                                                           float *__restrict__ out) {
+  const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (4 * b >= n) return;
+  uint32_t x0 = (uint32_t)b, x1 = c1, x2 = c2, x3 = 0u, k0 = s0, k1 = s1;
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * x0, hi0 = __umulhi(0xD2511F53u, x0);
+    const uint32_t lo1 = 0xCD9E8D57u * x2, hi1 = __umulhi(0xCD9E8D57u, x2);
+    const uint32_t y0 = hi1 ^ x1 ^ k0, y2 = hi0 ^ x3 ^ k1;
+    x0 = y0;
+    x1 = lo1;
+    x2 = y2;
+    x3 = lo0;
+  }
+  const uint32_t w[4] = {x0, x1, x2, x3};
+  double z[4];
+  for (int j = 0; j < 4; j += 2) {
+    const double u = ((double)w[j] + 0.5) * 0x1p-32, v = ((double)w[j + 1] + 0.5) * 0x1p-32;
+    const double r = sqrt(-2.0 * log(u));
+    double sn, cs;
+    sincospi(2.0 * v, &sn, &cs);
+    z[j] = r * cs;
+    z[j + 1] = r * sn;
+  }
+  for (int k = 0; k < 4; ++k)
+    if (4 * b + k < n) out[4 * b + k] = (float)z[k];
+}
+
 }  // namespace
+
+void launch_random_normals(uint64_t seed, uint64_t counter, int64_t n, float *out, hipStream_t s) {
+  const int64_t blocks = (n + 4 * kBlock - 1) / (4 * kBlock);
+  hipLaunchKernelGGL(k_random_normals, dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                     (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)counter,
+                     (uint32_t)(counter >> 32), n, out);
+}
 
 void launch_adam(const AdamArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_adam, dim3(grid_for(11 * a.n)), dim3(kBlock), 0, s, a);

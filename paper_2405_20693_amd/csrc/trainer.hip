@@ -124,6 +124,9 @@ struct gs_trainer {
   std::mt19937_64 rng;
   std::vector<int32_t> stack;
   std::vector<gs_view> batch;
+  // reserved plans (no allocation and no synchronization per iteration)
+  bool reserved = false;
+  int64_t res_gaussians = 0, res_proj_entries = 0, res_vox_entries = 0;
 };
 
 namespace {
@@ -155,6 +158,61 @@ gs_status clear_stats(gs_trainer *t) {
   if (hipMemsetAsync(t->st_sum, 0, sizeof(float) * (size_t)t->n, t->stream) != hipSuccess ||
       hipMemsetAsync(t->st_vis, 0, sizeof(int32_t) * (size_t)t->n, t->stream) != hipSuccess)
     return GS_EHIP;
+  return GS_OK;
+}
+
+// (Re)reserves the projection, voxel and loss plans for the current capacity
+// and 3x the given entry counts.
+gs_status reserve_plans(gs_trainer *t, int64_t proj_entries, int64_t vox_entries) {
+  const gs_train_config &c = t->cfg;
+  const int64_t cap = std::max(t->sets[0].cap, t->sets[1].cap);
+  const int D = c.tv_size;
+  const bool tv = c.lambda_tv > 0.f && D > 0;
+  gs_reserve r{};
+  r.max_gaussians = cap;
+  r.max_views = c.views_per_iter;
+  r.width = t->views[0].width;
+  r.height = t->views[0].height;
+  r.max_proj_entries = std::min<int64_t>(3 * std::max<int64_t>(proj_entries, 1024), 0xfffffffeLL);
+  TR_TRY(gs_plan_reserve(t->proj, &r, t->stream));
+  if (tv) {
+    gs_reserve v{};
+    v.max_gaussians = cap;
+    v.nx = std::min(D, t->grid.nx);
+    v.ny = std::min(D, t->grid.ny);
+    v.nz = std::min(D, t->grid.nz);
+    // the random block's entries vary with its position; a Gaussian meets at
+    // most every 8^3 tile of the block, which bounds them for any position
+    const int64_t tiles = (int64_t)((v.nx + 7) / 8) * ((v.ny + 7) / 8) * ((v.nz + 7) / 8);
+    v.max_vox_entries = std::min<int64_t>(std::max<int64_t>(cap * tiles, 1024), 0xfffffffeLL);
+    (void)vox_entries;
+    TR_TRY(gs_plan_reserve(t->vox, &v, t->stream));
+  }
+  gs_reserve l{};
+  l.max_views = c.views_per_iter;
+  l.width = t->views[0].width;
+  l.height = t->views[0].height;
+  l.max_tv_voxels = tv ? (int64_t)D * D * D : 0;
+  TR_TRY(gs_plan_reserve(t->loss, &l, t->stream));
+  t->reserved = true;
+  t->res_gaussians = cap;
+  t->res_proj_entries = r.max_proj_entries;
+  t->res_vox_entries = 0;  // bounded by construction (see above)
+  return GS_OK;
+}
+
+// At a synchronization point: fail if an iteration exceeded the reserved
+// tile lists; grow the reservation when the largest need passed half of it
+// or the parameter capacity grew.
+gs_status check_plans(gs_trainer *t) {
+  if (!t->reserved) return GS_OK;
+  int64_t pe = 0, ve = 0, unused = 0;
+  TR_TRY(gs_plan_check(t->proj, &pe, &unused));
+  if (t->cfg.lambda_tv > 0.f && t->cfg.tv_size > 0) TR_TRY(gs_plan_check(t->vox, &unused, &ve));
+  const int64_t cap = std::max(t->sets[0].cap, t->sets[1].cap);
+  (void)ve;
+  if (2 * pe > t->res_proj_entries || cap > t->res_gaussians)
+    return reserve_plans(t, std::max(pe, t->res_proj_entries / 3), 0);
   return GS_OK;
 }
 
@@ -256,7 +314,18 @@ gs_status step(gs_trainer *t, const int32_t *view_idx, const int32_t *tv_offset,
                     (float)(c.lr_density * f), it1};
   TR_TRY(gs_adam_step(&t->sets[t->cur].p, t->n, &gr, &ac, t->stream));
   t->iter = it1;
-  if (densify_due(c, it1)) TR_TRY(densify(t, normals));
+  if (densify_due(c, it1)) {
+    TR_TRY(densify(t, normals));
+    TR_TRY(check_plans(t));
+  }
+  if (!t->reserved) {
+    // the first iteration ran with allocating plans: size the reservation
+    // from its tile-list entries
+    int64_t pe = 0, ve = 0;
+    TR_TRY(gs_plan_status(t->proj, nullptr, &pe));
+    if (tv) TR_TRY(gs_plan_status(t->vox, nullptr, &ve));
+    TR_TRY(reserve_plans(t, pe, ve));
+  }
   return GS_OK;
 }
 
@@ -384,8 +453,6 @@ gs_status gs_trainer_run(gs_trainer *t, int32_t iters, float *losses) {
   const gs_train_config &c = t->cfg;
   TR_TRY(grow(t->loss_dev, t->loss_cap, 4 * (size_t)iters));
   std::vector<int32_t> idx(c.views_per_iter);
-  std::vector<float> z;
-  std::normal_distribution<float> normal(0.f, 1.f);
   for (int32_t k = 0; k < iters; ++k) {
     for (int b = 0; b < c.views_per_iter; ++b) {
       if (t->stack.empty())
@@ -403,17 +470,15 @@ gs_status gs_trainer_run(gs_trainer *t, int32_t iters, float *losses) {
     }
     const float *nrm = nullptr;
     if (densify_due(c, t->iter + 1)) {
-      z.resize(6 * (size_t)std::max<int64_t>(t->n, 1));
-      for (float &x : z) x = normal(t->rng);
-      TR_TRY(grow(t->normals, t->normals_cap, z.size()));
-      if (hipMemcpyAsync(t->normals, z.data(), sizeof(float) * z.size(), hipMemcpyHostToDevice,
-                         t->stream) != hipSuccess)
-        return GS_EHIP;
+      // split draws on the device: counter = index of this densification
+      const size_t nz = 6 * (size_t)std::max<int64_t>(t->n, 1);
+      TR_TRY(grow(t->normals, t->normals_cap, nz));
+      TR_TRY(gs_random_normals(c.seed, (uint64_t)t->iter, (int64_t)nz, t->normals, t->stream));
       nrm = t->normals;
     }
     TR_TRY(step(t, idx.data(), off, nrm, t->loss_dev + 4 * (size_t)k));
-    if (nrm && hipStreamSynchronize(t->stream) != hipSuccess) return GS_EHIP;  // host draws reused
   }
+  TR_TRY(check_plans(t));
   if (losses) {
     std::vector<float> h(4 * (size_t)iters);
     if (hipMemcpyAsync(h.data(), t->loss_dev, sizeof(float) * h.size(), hipMemcpyDeviceToHost,
@@ -469,7 +534,7 @@ gs_status gs_trainer_evaluate(gs_trainer *t, const gs_grid *grid, float *volume,
                               t->aux, t->stream));
     g.density = t->dens_corr;
   }
-  TR_TRY(gs_voxelize_fwd(&g, grid, t->cfg.cutoff, volume, t->vox, t->stream));
+  TR_TRY(gs_voxelize_fwd(&g, grid, t->cfg.cutoff, volume, t->aux, t->stream));
   if (gt)
     TR_TRY(gs_volume_metrics(volume, gt, grid->nx, grid->ny, grid->nz, psnr, ssim, t->aux,
                              t->stream));

@@ -66,6 +66,15 @@ def project_backward_stats(mean, scale, quat, density, views: Views, grad_image,
     return grads
 
 
+def random_normals(seed, counter, n, out=None):
+    """n standard normal draws (Philox4x32-10 + Box-Muller) on the device."""
+    if out is None:
+        out = torch.empty(max(int(n), 1), device="cuda", dtype=torch.float32)
+    N.call("gs_random_normals", int(seed) & 0xFFFFFFFFFFFFFFFF, int(counter) & 0xFFFFFFFFFFFFFFFF,
+           int(n), _dev(out, "out"), _stream())
+    return out[:int(n)]
+
+
 def adam_step(state: ParamState, n, grads, lrs, step):
     """grads: (mean, scale, quat, density) gradients w.r.t. the activated
     parameters; lrs: dict with keys mean, scale, quat, density."""

@@ -353,3 +353,12 @@ def test_trainer_reconstruction_improves_and_rectification_wins(ops, tr):
     assert results[1][0] > results[0][0] + 0.3
     assert results[1][1] > results[0][1]
     assert results[1][2] != wl.gaussians.n      # adaptive control ran
+
+
+def test_random_normals_match_oracle(tr):
+    """The device generator reproduces the oracle's Philox4x32-10 +
+    Box-Muller draws (bit-exact words; the transform in double, rounded)."""
+    for seed, counter, n in ((0, 0, 37), (12345, 7, 4001), (2 ** 40 + 3, 2 ** 33 + 5, 64)):
+        got = tr.random_normals(seed, counter, n).cpu().numpy()
+        ref = ot.random_normals(seed, counter, n)
+        np.testing.assert_allclose(got, ref, rtol=1e-6, atol=1e-6)

@@ -181,3 +181,23 @@ def test_volume_metrics():
         a, b = np.moveaxis(vol / r, ax, 0), np.moveaxis(gt / r, ax, 0)
         per_axis.append(np.mean([ssim2(a[i], b[i]) for i in range(a.shape[0])]))
     assert abs(ot.volume_ssim(vol, gt) - np.mean(per_axis)) < 1e-12
+
+
+def test_philox_known_answers():
+    """Known-answer vectors of Philox4x32-10 published with the generator."""
+    assert ot.philox4x32_10((0, 0, 0, 0), (0, 0)) == (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)
+    f = 0xFFFFFFFF
+    assert ot.philox4x32_10((f, f, f, f), (f, f)) == (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)
+    assert ot.philox4x32_10((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344),
+                            (0xA4093822, 0x299F31D0)) == (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1)
+
+
+def test_random_normals_statistics():
+    z = ot.random_normals(seed=12345, counter=7, n=40000)
+    assert abs(z.mean()) < 0.02 and abs(z.var() - 1) < 0.03
+    from scipy import stats
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+    # other counters and seeds give other draws; a prefix is stable
+    assert not np.allclose(z[:8], ot.random_normals(12345, 8, 8))
+    assert not np.allclose(z[:8], ot.random_normals(12346, 7, 8))
+    np.testing.assert_array_equal(z[:10], ot.random_normals(12345, 7, 10))
