@@ -190,6 +190,40 @@ __device__ inline bool box_hits(const float (*s)[kBlock], int i, float x0, float
          (cz + rz >= z0) && (cz - rz <= z0 + e);
 }
 
+// Upper bound of the exponent q' (concave: the conic is negative definite)
+// over the voxel-centre box [x0, x0 + 3] x [y0, y0 + 3] x [z0, z0 + 3] of a
+// 4^3 sub-cube: two sweeps of coordinate ascent give a point y of the box,
+// and by concavity q'(x) <= q'(y) + grad q'(y) . (x - y), whose maximum over
+// the box is the bound.  It never falls below the true maximum, so culling a
+// record whose bound is under the cutoff threshold drops no term; for
+// elongated Gaussians it is far tighter than the axis-aligned box.
+__device__ inline bool box_may_reach(const float (*s)[kBlock], int i, float x0, float y0, float z0,
+                                     float thr) {
+  const float e = (float)(kVSub - 1);
+  const float c00 = s[3][i], c01 = s[4][i], c02 = s[5][i], c11 = s[6][i], c12 = s[7][i],
+              c22 = s[8][i];
+  const float lx = x0 - s[0][i], ly = y0 - s[1][i], lz = z0 - s[2][i];
+  const float hx = lx + e, hy = ly + e, hz = lz + e;
+  const float ix = -0.5f / c00, iy = -0.5f / c11, iz = -0.5f / c22;
+  float dx = fminf(fmaxf(0.f, lx), hx), dy = fminf(fmaxf(0.f, ly), hy), dz = fminf(fmaxf(0.f, lz), hz);
+  for (int sweep = 0; sweep < 2; ++sweep) {
+    dx = fminf(fmaxf((c01 * dy + c02 * dz) * ix, lx), hx);
+    dy = fminf(fmaxf((c01 * dx + c12 * dz) * iy, ly), hy);
+    dz = fminf(fmaxf((c02 * dx + c12 * dy) * iz, lz), hz);
+  }
+  const float qy = dx * (c00 * dx + c01 * dy + c02 * dz) + dy * (c11 * dy + c12 * dz) + c22 * dz * dz;
+  const float gx = 2.f * c00 * dx + c01 * dy + c02 * dz;
+  const float gy = c01 * dx + 2.f * c11 * dy + c12 * dz;
+  const float gz = c02 * dx + c12 * dy + 2.f * c22 * dz;
+  const float tx = gx > 0.f ? gx * (hx - dx) : gx * (lx - dx);
+  const float ty = gy > 0.f ? gy * (hy - dy) : gy * (ly - dy);
+  const float tz = gz > 0.f ? gz * (hz - dz) : gz * (lz - dz);
+  const float ub = qy + tx + ty + tz;
+  // FP32 rounding margin of the bound and of the kernels' own q'
+  const float margin = 1e-5f * (fabsf(qy) + fabsf(tx) + fabsf(ty) + fabsf(tz)) + 1e-5f;
+  return ub + margin >= thr;
+}
+
 __device__ inline float vox_q(const float (*s)[kBlock], int e, float dx, float dy, float dz) {
   return dx * (s[3][e] * dx + s[4][e] * dy + s[5][e] * dz) + dy * (s[6][e] * dy + s[7][e] * dz) +
          s[8][e] * dz * dz;
@@ -232,7 +266,8 @@ __global__ __launch_bounds__(kBlock) void k_vox_fwd(VoxArgs a, const Rec3 *__res
     for (int k = 0; k < 2; ++k) {
       for (int c0 = 0; c0 < n; c0 += 64) {
         const int i = c0 + lane;
-        const bool hit = (i < n) && box_hits(s, i, ox[k], oy[k], oz[k]);
+        const bool hit = (i < n) && box_hits(s, i, ox[k], oy[k], oz[k]) &&
+                         box_may_reach(s, i, ox[k], oy[k], oz[k], a.thr);
         uint64_t mask = __ballot(hit);
         while (mask) {
           const int e = c0 + __builtin_ctzll(mask);
@@ -337,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_vox_bwd(VoxArgs a, const Rec3 *__res
       int qn = 0;
       for (int c0 = 0; c0 < n; c0 += 64) {
         const int i = c0 + lane;
-        const bool hit = (i < n) && box_hits(s, i, ox, oy, oz);
+        const bool hit = (i < n) && box_hits(s, i, ox, oy, oz) && box_may_reach(s, i, ox, oy, oz, a.thr);
         uint64_t mask = __ballot(hit);
         if (hit)
           s_q[w][qn + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
