@@ -180,7 +180,9 @@ GS_API gs_status gs_trainer_run(gs_trainer *tr, int32_t iters, float *losses);
 /* One iteration with explicit draws: view_idx [views_per_iter] (host),
  * tv_offset[3] (host, voxel offset of the TV block in the grid), normals
  * (device [n][2][3] for the current count n, used only if this iteration
- * densifies; NULL otherwise).  loss: host, may be NULL (then no sync). */
+ * densifies; NULL otherwise).  loss: host, may be NULL (then no sync); with a
+ * loss the call also checks the trainer's reserved plans (GS_EOVERFLOW if an
+ * iteration's tile lists exceeded them). */
 GS_API gs_status gs_trainer_step(gs_trainer *tr, const int32_t *view_idx, const int32_t *tv_offset,
                                  const float *normals, float *loss);
 

@@ -443,6 +443,7 @@ gs_status gs_trainer_step(gs_trainer *t, const int32_t *view_idx, const int32_t 
         hipStreamSynchronize(t->stream) != hipSuccess)
       return GS_EHIP;
     *loss = h[0] + t->cfg.lambda_tv * h[3];
+    TR_TRY(check_plans(t));  // synchronized anyway: report any reservation overflow
   }
   return GS_OK;
 }
