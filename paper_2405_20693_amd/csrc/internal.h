@@ -223,21 +223,21 @@ __device__ inline void project_one(const Gauss &G, const DevView &V, Proj2 &P) {
 
 // Minimum over a rectangle [x0,x1] x [y0,y1] (offsets from the centre) of the
 // positive-definite form a dx^2 + b dx dy + c dy^2; ia = 1/(2a), ic = 1/(2c).
+// With the centre outside the rectangle the minimum lies on an edge whose
+// half-plane excludes the centre (at a minimum with only the constraints of
+// one axis active, the gradient condition puts the centre beyond that edge;
+// a corner minimum with neither edge facing the centre would force the corner
+// to be the centre).  So only the facing x edge and the facing y edge are
+// searched; where no x (y) edge faces the centre, the other axis' edge holds
+// the minimum and the extra candidate is just some point of the rectangle.
 __device__ inline float rect_min_form(float a, float b, float c, float ia, float ic, float x0,
                                       float x1, float y0, float y1) {
   if (x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f) return 0.f;
-  float best;
-  {
-    float dy = fminf(fmaxf(-b * x0 * ic, y0), y1);
-    best = a * x0 * x0 + b * x0 * dy + c * dy * dy;
-    dy = fminf(fmaxf(-b * x1 * ic, y0), y1);
-    best = fminf(best, a * x1 * x1 + b * x1 * dy + c * dy * dy);
-    float dx = fminf(fmaxf(-b * y0 * ia, x0), x1);
-    best = fminf(best, a * dx * dx + b * dx * y0 + c * y0 * y0);
-    dx = fminf(fmaxf(-b * y1 * ia, x0), x1);
-    best = fminf(best, a * dx * dx + b * dx * y1 + c * y1 * y1);
-  }
-  return best;
+  const float xe = x0 > 0.f ? x0 : x1;
+  const float ye = y0 > 0.f ? y0 : y1;
+  const float dy = fminf(fmaxf(-b * xe * ic, y0), y1);
+  const float dx = fminf(fmaxf(-b * ye * ia, x0), x1);
+  return fminf(a * xe * xe + b * xe * dy + c * dy * dy, a * dx * dx + b * dx * ye + c * ye * ye);
 }
 
 // Workgroup index remapped so that each XCD (workgroups are dealt round-robin

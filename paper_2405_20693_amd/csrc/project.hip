@@ -267,7 +267,10 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
                                                        const uint32_t *__restrict__ tile_start,
                                                        float *__restrict__ image,
                                                        float *__restrict__ partial) {
+  // staged records: (pu, pv, c00, c01), (c11, rho, 1/(2a), 1/(2c)) with a = -c00,
+  // c = -c11 the positive form, and log2|rho|, computed once per workgroup
   __shared__ float4 s_r0[kBlock], s_r1[kBlock];
+  __shared__ float s_lr[kBlock];
   // per wave: the kept records' coefficients, compacted, two float4 each
   __shared__ float4 s_k[4][64][2];
   const int wi = xcd_remap(blockIdx.x, gridDim.x);
@@ -293,8 +296,10 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
     if (tid < n) {
       const uint32_t g = list[base + tid].x;
       const float4 *p = reinterpret_cast<const float4 *>(rv + g);
-      s_r0[tid] = p[0];
-      s_r1[tid] = p[1];
+      const float4 r0 = p[0], r1 = p[1];
+      s_r0[tid] = r0;
+      s_r1[tid] = make_float4(r1.x, r1.y, -0.5f / r0.z, -0.5f / r1.x);
+      s_lr[tid] = __log2f(fabsf(r1.y));
     }
     __syncthreads();
     for (int c0 = 0; c0 < n; c0 += 64) {
@@ -305,12 +310,11 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
         const float4 r0 = s_r0[i], r1 = s_r1[i];
         const float c00 = r0.z, c01 = r0.w, c11 = r1.x, rho = r1.y;
         const float u = r0.x - cxs, vv = r0.y - cys;  // centre relative to the sub-tile centre
-        const float aa = -c00, bb = -c01, cc = -c11;
-        const float m = rect_min_form(aa, bb, cc, 0.5f / aa, 0.5f / cc, -hs - u, hs - u, -hs - vv,
+        const float m = rect_min_form(-c00, -c01, -c11, r1.z, r1.w, -hs - u, hs - u, -hs - vv,
                                       hs - vv);
         hit = m <= a.qmax && rho != 0.f;
         if (hit) {
-          const float lr = __log2f(fabsf(rho));
+          const float lr = s_lr[i];
           const float K0 = u * (c00 * u + c01 * vv) + c11 * vv * vv + lr;
           const float K1 = -(2.f * c00 * u + c01 * vv);
           const float K2 = -(c01 * u + 2.f * c11 * vv);
@@ -391,15 +395,21 @@ void launch_render_fwd(const ProjArgs &a, const Rec2 *rec, const uint2 *list,
 
 // ------------------------------------------------------ render backward --
 
+constexpr float kChainRange = 120.f;  // exp2 range of the multiplicative walk
+
 // Same tiling as the forward.  For the upstream gradient G of one tile and
 // each (record, sub-tile) pair that the cutoff keeps, one lane walks the
 // sub-tile's 64 pixels and accumulates the moments
 //   S0 = sum G e, S1 = sum G e dx, S2 = sum G e dy,
 //   S3 = sum G e dx^2, S4 = sum G e dx dy, S5 = sum G e dy^2
 // (pixel units, e = exp2(q'), d = pixel - centre), which determine the
-// gradients with respect to rho_hat, the centre and the conic.  Lanes are
-// entries, so no cross-lane reduction is needed; the four waves' moments are
-// summed in a fixed order and written to the entry's slot (deterministic).
+// gradients with respect to rho_hat, the centre and the conic.  Wave w culls
+// the batch's records against sub-tile w; the workgroup then walks the kept
+// pairs of all four sub-tiles as one queue in chunks of 64, dealt to the
+// waves in turn, so that lanes stay busy and load is balanced.  Lanes are
+// pairs, so no cross-lane reduction is needed; each pair's moments depend on
+// that pair alone, and the four sub-tiles' moments are summed in a fixed
+// order and written to the entry's slot (deterministic).
 __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *__restrict__ rec,
                                                        const uint2 *__restrict__ list,
                                                        const uint32_t *__restrict__ tile_start,
@@ -410,6 +420,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *_
   __shared__ __align__(16) float s_G[kTile * kTile];
   __shared__ float s_acc[4][6][kBlock];
   __shared__ uint16_t s_q[4][kBlock];
+  __shared__ int s_cnt[2][4];  // per sub-tile: chained pairs, per-pixel exp2 pairs
   const int wi = xcd_remap(blockIdx.x, gridDim.x);
   const int item = wi / a.parts, part = wi - item * a.parts;
   const int v = item / a.T, t = item - v * a.T;
@@ -430,6 +441,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *_
   list_part(min(tile_start[item], a.cap), min(tile_start[item + 1], a.cap), part, a.parts, beg,
             end);
   const Rec2 *rv = rec + (int64_t)v * a.M;
+  const float ethr = __builtin_amdgcn_exp2f(a.thr);  // the cutoff on e = exp2(q)
   for (uint32_t base = beg; base < end; base += kBlock) {
     const int n = (int)min((uint32_t)kBlock, end - base);
     __syncthreads();
@@ -449,73 +461,135 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *_
 #pragma unroll
       for (int ww = 0; ww < 4; ++ww) s_acc[ww][k][tid] = 0.f;
     __syncthreads();
-    // compact the records that meet this wave's sub-tile
-    int qn = 0;
+    // Compact the records that meet this wave's sub-tile into two queues.
+    // Entries whose form stays below kChainRange over the whole sub-tile
+    // (its maximum is at a corner) go to the front: their walk steps
+    // e = exp2(q) by multiplication, along a row by r = exp2(q(x+1) - q(x)),
+    // r itself by exp2(2 c00), and down the first column likewise, so every
+    // chained value and factor is a normal FP32 number and six exp2 per walk
+    // replace 64.  The others go to the back and evaluate exp2(q) per pixel
+    // with q forward-differenced.  Each entry's path is its own, so its
+    // moments do not depend on which entries share its wave.
+    int qn = 0, qs = 0;
     for (int c0 = 0; c0 < n; c0 += 64) {
       const int i = c0 + lane;
-      bool hit = false;
+      bool hit = false, steep = false;
       if (i < n) {
         const float pu = s_pu[i], pv = s_pv[i];
-        float m = rect_min_form(-s_c00[i], -s_c01[i], -s_c11[i], s_ia[i], s_ic[i], rx0 - pu,
-                                rx1 - pu, ry0 - pv, ry1 - pv);
+        const float fa = -s_c00[i], fb = -s_c01[i], fc = -s_c11[i];
+        const float x0 = rx0 - pu, x1 = rx1 - pu, y0 = ry0 - pv, y1 = ry1 - pv;
+        float m = rect_min_form(fa, fb, fc, s_ia[i], s_ic[i], x0, x1, y0, y1);
         hit = m <= a.qmax;
+        const float ax0 = fa * x0 * x0, ax1 = fa * x1 * x1, cy0 = fc * y0 * y0, cy1 = fc * y1 * y1;
+        const float fmax = fmaxf(fmaxf(fmaf(fb * x0, y0, ax0 + cy0), fmaf(fb * x1, y0, ax1 + cy0)),
+                                 fmaxf(fmaf(fb * x0, y1, ax0 + cy1), fmaf(fb * x1, y1, ax1 + cy1)));
+        steep = !(fmax <= kChainRange);
       }
-      uint64_t mask = __ballot(hit);
-      if (hit) s_q[w][qn + lanes_below(mask)] = (uint16_t)i;
-      qn += __popcll(mask);
+      const uint64_t mc = __ballot(hit && !steep), ms = __ballot(hit && steep);
+      if (hit && !steep) s_q[w][qn + lanes_below(mc)] = (uint16_t)i;
+      if (hit && steep) s_q[w][kBlock - 1 - (qs + lanes_below(ms))] = (uint16_t)i;
+      qn += __popcll(mc);
+      qs += __popcll(ms);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int qb = 0; qb < qn; qb += 64) {
-      const int j = qb + lane;
-      const bool active = j < qn;
-      const int e = active ? (int)s_q[w][j] : 0;
-      const float pu = s_pu[e], pv = s_pv[e];
-      const float c00 = s_c00[e], c01 = s_c01[e], c11 = s_c11[e];
-      const float dd = 2.f * c00;
-      const float dx0 = rx0 - pu;
-      const float thr = a.thr;
-      // per-column sums over the rows of G e, G e dy, G e dy^2; the x moments
-      // follow from them once per walk (dx is constant down a column)
-      float C0[kSub], C2[kSub], C5[kSub];
+    if (lane == 0) {
+      s_cnt[0][w] = qn;
+      s_cnt[1][w] = qs;
+    }
+    __syncthreads();
+    // The workgroup's queue: the chained pairs of sub-tiles 0..3, then their
+    // per-pixel pairs, in chunks of 64 (a chunk holds pairs of one kind).
+    const int kc = (s_cnt[0][0] + s_cnt[0][1] + s_cnt[0][2] + s_cnt[0][3] + 63) >> 6;
+    const int kall = kc + ((s_cnt[1][0] + s_cnt[1][1] + s_cnt[1][2] + s_cnt[1][3] + 63) >> 6);
+    for (int k = w; k < kall; k += 4) {
+      {
+        const bool chain = k < kc;
+        const int kind = chain ? 0 : 1;
+        const int b1 = s_cnt[kind][0], b2 = b1 + s_cnt[kind][1], b3 = b2 + s_cnt[kind][2];
+        const int btot = b3 + s_cnt[kind][3];
+        int pidx = (chain ? k : k - kc) * 64 + lane;
+        const bool active = pidx < btot;
+        const int sw = (pidx >= b1) + (pidx >= b2) + (pidx >= b3);
+        pidx -= sw == 0 ? 0 : sw == 1 ? b1 : sw == 2 ? b2 : b3;
+        const int e = active ? (int)s_q[sw][chain ? pidx : kBlock - 1 - pidx] : 0;
+        const int pxl = (sw & 1) * kSub, pyl = (sw >> 1) * kSub;  // the pair's sub-tile
+        const float ox = (float)(tx * kTile + pxl), oy = (float)(ty * kTile + pyl);
+        const float *Gsub = s_G + pyl * kTile + pxl;
+        const float pu = s_pu[e], pv = s_pv[e];
+        const float c00 = s_c00[e], c01 = s_c01[e], c11 = s_c11[e];
+        const float dx0 = ox - pu, dy0 = oy - pv;
+        // per-column sums over the rows of G e, G e dy, G e dy^2; the x moments
+        // follow from them once per walk (dx is constant down a column)
+        float C0[kSub], C2[kSub], C5[kSub];
 #pragma unroll
-      for (int col = 0; col < kSub; ++col) C0[col] = C2[col] = C5[col] = 0.f;
+        for (int col = 0; col < kSub; ++col) C0[col] = C2[col] = C5[col] = 0.f;
+        if (chain) {
+          float e_row = __builtin_amdgcn_exp2f(dx0 * (c00 * dx0 + c01 * dy0) + c11 * dy0 * dy0);
+          float rx_row = __builtin_amdgcn_exp2f(c00 * (2.f * dx0 + 1.f) + c01 * dy0);
+          float hr = __builtin_amdgcn_exp2f(c01 * dx0 + c11 * (2.f * dy0 + 1.f));
+          const float rxx = __builtin_amdgcn_exp2f(2.f * c00);
+          const float rxy = __builtin_amdgcn_exp2f(c01);
+          const float ryy = __builtin_amdgcn_exp2f(2.f * c11);
 #pragma unroll 2
-      for (int r = 0; r < kSub; ++r) {
-        const float dy = ry0 + (float)r - pv;
-        const float dy2 = dy * dy;
-        float q = dx0 * (c00 * dx0 + c01 * dy) + c11 * dy2;
-        float d = c00 * (2.f * dx0 + 1.f) + c01 * dy;
-        const float4 *Grow = reinterpret_cast<const float4 *>(s_G + (syl + r) * kTile + sxl);
-        const float4 ga = Grow[0], gb = Grow[1];
-        const float Gr[kSub] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
+          for (int r = 0; r < kSub; ++r) {
+            const float dy = dy0 + (float)r;
+            const float dy2 = dy * dy;
+            const float4 *Grow = reinterpret_cast<const float4 *>(Gsub + r * kTile);
+            const float4 ga = Grow[0], gb = Grow[1];
+            const float Gr[kSub] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
+            float ev = e_row, rx = rx_row;
+#pragma unroll
+            for (int col = 0; col < kSub; ++col) {
+              const float ge = (ev >= ethr) ? ev * Gr[col] : 0.f;
+              C0[col] += ge;
+              C2[col] = fmaf(ge, dy, C2[col]);
+              C5[col] = fmaf(ge, dy2, C5[col]);
+              ev *= rx;
+              rx *= rxx;
+            }
+            e_row *= hr;
+            hr *= ryy;
+            rx_row *= rxy;
+          }
+        } else {
+          const float dd = 2.f * c00;
+          const float thr = a.thr;
+#pragma unroll 2
+          for (int r = 0; r < kSub; ++r) {
+            const float dy = oy + (float)r - pv;
+            const float dy2 = dy * dy;
+            float q = dx0 * (c00 * dx0 + c01 * dy) + c11 * dy2;
+            float d = c00 * (2.f * dx0 + 1.f) + c01 * dy;
+            const float4 *Grow = reinterpret_cast<const float4 *>(Gsub + r * kTile);
+            const float4 ga = Grow[0], gb = Grow[1];
+            const float Gr[kSub] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
+#pragma unroll
+            for (int col = 0; col < kSub; ++col) {
+              const float ex = __builtin_amdgcn_exp2f(q) * Gr[col];
+              const float ge = (q >= thr) ? ex : 0.f;
+              C0[col] += ge;
+              C2[col] = fmaf(ge, dy, C2[col]);
+              C5[col] = fmaf(ge, dy2, C5[col]);
+              q += d;
+              d += dd;
+            }
+          }
+        }
+        float S0 = 0.f, S1 = 0.f, S2 = 0.f, S3 = 0.f, S4 = 0.f, S5 = 0.f;
 #pragma unroll
         for (int col = 0; col < kSub; ++col) {
-          const float ex = __builtin_amdgcn_exp2f(q) * Gr[col];
-          const float ge = (q >= thr) ? ex : 0.f;
-          C0[col] += ge;
-          C2[col] = fmaf(ge, dy, C2[col]);
-          C5[col] = fmaf(ge, dy2, C5[col]);
-          q += d;
-          d += dd;
+          const float dx = dx0 + (float)col;
+          S0 += C0[col];
+          const float t1 = C0[col] * dx;
+          S1 += t1;
+          S3 = fmaf(t1, dx, S3);
+          S2 += C2[col];
+          S4 = fmaf(C2[col], dx, S4);
+          S5 += C5[col];
         }
-      }
-      float S0 = 0.f, S1 = 0.f, S2 = 0.f, S3 = 0.f, S4 = 0.f, S5 = 0.f;
-#pragma unroll
-      for (int col = 0; col < kSub; ++col) {
-        const float dx = dx0 + (float)col;
-        S0 += C0[col];
-        const float t1 = C0[col] * dx;
-        S1 += t1;
-        S3 = fmaf(t1, dx, S3);
-        S2 += C2[col];
-        S4 = fmaf(C2[col], dx, S4);
-        S5 += C5[col];
-      }
-      if (active) {
-        s_acc[w][0][e] = S0; s_acc[w][1][e] = S1; s_acc[w][2][e] = S2;
-        s_acc[w][3][e] = S3; s_acc[w][4][e] = S4; s_acc[w][5][e] = S5;
+        if (active) {
+          s_acc[sw][0][e] = S0; s_acc[sw][1][e] = S1; s_acc[sw][2][e] = S2;
+          s_acc[sw][3][e] = S3; s_acc[sw][4][e] = S4; s_acc[sw][5][e] = S5;
+        }
       }
     }
     __syncthreads();

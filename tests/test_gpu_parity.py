@@ -147,6 +147,26 @@ def test_cone_gradients(ops, cutoff):
     assert el <= 1.0 and nr <= 1.0
 
 
+def test_cone_gradients_thin_and_wide(ops):
+    """Projected widths from a third of a pixel to several pixels: the
+    backward walks of the wide ones step exp2 by multiplication, those of the
+    thin ones (form beyond the multiplicative range over an 8x8 sub-tile)
+    evaluate exp2 per pixel; both against the oracle."""
+    g = scenes.random_scene(43, 300, lo=0.006, hi=0.1, box=0.5)
+    th = [0.2, 2.1, 4.4]
+    views = ops.Views.cone(th, 13.64, 20.46, 80, 72, 0.045)
+    ov = [oracle.cone_view(t, 13.64, 20.46, 80, 72, 0.045) for t in th]
+    params = [torch.from_numpy(np.asarray(a, np.float64)) for a in (g.mean, g.scale, g.quat, g.density)]
+    with torch.no_grad():
+        pr = oracle.project_gaussians(*params, ov[0])
+    A = torch.stack([torch.stack([pr["A"][0], pr["A"][1]], -1), torch.stack([pr["A"][1], pr["A"][2]], -1)], -2)
+    sig_px = 1.0 / torch.sqrt(torch.linalg.eigvalsh(A)[:, 1]).numpy() / 0.045
+    assert (sig_px < 0.6).mean() > 0.1 and (sig_px > 1.5).mean() > 0.3
+    el, nr = _check_proj_grad(ops, g, views, ov, 6)
+    _report("cone grads thin and wide", max(el, nr))
+    assert el <= 1.0 and nr <= 1.0
+
+
 def test_parallel_gradients(ops):
     from scipy.spatial.transform import Rotation
     g = scenes.random_scene(42, 200, lo=0.03, hi=0.12, box=0.6)
