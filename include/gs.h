@@ -173,7 +173,8 @@ GS_API gs_status gs_view_cone(double theta, float src_obj, float src_det, int32_
  * height.  image: [n_views][height][width], overwritten.
  * plan: may be NULL (a temporary workspace is allocated and freed, and the
  * stream is synchronized); with a plan, the binning is kept for a following
- * gs_project_bwd on the same arguments.  Synchronizes `stream` once. */
+ * gs_project_bwd on the same arguments.  Synchronizes `stream` once.
+ * At most 2^28 - 1 Gaussians per projection call (GS_EUNSUPPORTED beyond). */
 GS_API gs_status gs_project_fwd(const gs_gaussians *g, const gs_view *views, int32_t n_views,
                          float cutoff, float *image, gs_plan *plan, hipStream_t stream);
 

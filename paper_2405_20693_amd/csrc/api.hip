@@ -355,6 +355,8 @@ gs_status proj_bin(gs_plan *pl, const gs_gaussians *g, const gs_view *views, int
   a.T = a.TX * a.TY;
   if (a.T > kMaxTilesPerGroup)
     return fail(GS_EUNSUPPORTED, "detector has more than 16384 tiles of 16x16 pixels");
+  if (a.M > (int64_t)kEntryIndexMask)
+    return fail(GS_EUNSUPPORTED, "projection of more than 2^28-1 Gaussians in one call");
   // binning chunks: 4096 Gaussians, halved while fewer than 512 (view, chunk)
   // workgroups would run (few views); render: parts per tile list so that
   // about 8192 workgroups run (one part when there are that many tiles)

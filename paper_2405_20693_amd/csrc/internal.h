@@ -230,6 +230,12 @@ __device__ inline void project_one(const Gauss &G, const DevView &V, Proj2 &P) {
 // to be the centre).  So only the facing x edge and the facing y edge are
 // searched; where no x (y) edge faces the centre, the other axis' edge holds
 // the minimum and the extra candidate is just some point of the rectangle.
+// Tile-list entry (Gaussian index | sub-tile mask << kEntryMaskShift, backward
+// slot): bit w of the mask is set when the cutoff ellipse meets 8x8 sub-tile w
+// of the 16x16 tile (w = (x half) + 2 (y half)).
+constexpr int kEntryMaskShift = 28;
+constexpr uint32_t kEntryIndexMask = (1u << kEntryMaskShift) - 1u;
+
 __device__ inline float rect_min_form(float a, float b, float c, float ia, float ic, float x0,
                                       float x1, float y0, float y1) {
   if (x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f) return 0.f;

@@ -192,6 +192,12 @@ void launch_hist_colscan(int groups, int C, int T, uint32_t *hist, uint32_t *til
 
 // Grid (C, V).  Writes each Gaussian's tile entries at its tiles' cursors and
 // the base index of its backward slots (Gaussian order within the chunk).
+// Lanes take entries, not Gaussians: after the scan of the 256 Gaussians'
+// entry counts, lane i handles entries i, i + 256, ... and finds its Gaussian
+// by binary search of the staged offsets, so Gaussians covering many tiles
+// do not idle the rest of their wave.  Each entry carries the mask of the
+// tile's 8x8 sub-tiles that the cutoff ellipse meets (exact minimum of the
+// quadratic form over each sub-tile's pixel-centre rectangle).
 __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 *__restrict__ rec,
                                                          const uint32_t *__restrict__ hist,
                                                          const uint32_t *__restrict__ tile_start,
@@ -202,6 +208,11 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
                                                          const unsigned long long *totals) {
   extern __shared__ uint32_t cur[];
   __shared__ uint32_t sh4[4];
+  __shared__ uint32_t s_off[kBlock + 1];  // exclusive entry offsets of the 256 Gaussians
+  __shared__ uint32_t s_org[kBlock];      // rectangle origin tx0 | ty0 << 16
+  __shared__ float s_w[kBlock];           // rectangle width in tiles
+  __shared__ float s_pu[kBlock], s_pv[kBlock], s_fa[kBlock], s_fb[kBlock], s_fc[kBlock];
+  __shared__ float s_ia[kBlock], s_ic[kBlock];
   const int c = blockIdx.x, v = blockIdx.y, tid = threadIdx.x;
   if (c == 0 && v == 0 && tid == 0) {  // the binning kernels of this call have finished
     ctl[2] = ctl[0];
@@ -213,7 +224,6 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
   const uint32_t *h = hist + ((int64_t)v * a.C + c) * a.T;
   const uint32_t *ts = tile_start + (int64_t)v * a.T;
   for (int t = tid; t < a.T; t += kBlock) cur[t] = ts[t] + h[t];
-  __syncthreads();
   uint32_t base = chunk_start[v * a.C + c];
   const int64_t g0 = (int64_t)c * kBlock * a.cpt;
   for (int k = 0; k < a.cpt; ++k) {
@@ -222,22 +232,57 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
     int64_t g = gk + tid;
     bool valid = g < a.M;
     Rect2 rc{1, 0, 0, 0};
+    Rec2 r{};
     if (valid) {
-      const Rec2 &r = rec[(int64_t)v * a.M + g];
+      r = rec[(int64_t)v * a.M + g];
       rc = unpack_rect(r.r0, r.r1);
     }
     int n = valid ? rect_count(rc) : 0;
     uint32_t total;
-    uint32_t ex = block_excl_scan((uint32_t)n, sh4, total);
+    uint32_t ex = block_excl_scan((uint32_t)n, sh4, total);  // synchronizes the workgroup
     if (valid) offsets[(int64_t)v * a.M + g] = base + ex;
-    uint32_t slot = base + ex;  // slots of this (view, Gaussian): its tiles in row-major order
-    for (int ty = rc.y0; ty <= rc.y1 && n; ++ty)
-      for (int tx = rc.x0; tx <= rc.x1; ++tx) {
-        uint32_t pos = atomicAdd(&cur[ty * a.TX + tx], 1u);
-        if (pos < a.cap) list[pos] = make_uint2((uint32_t)g, slot);
-        ++slot;
+    s_off[tid] = ex;
+    if (tid == 0) s_off[kBlock] = total;
+    s_org[tid] = (uint32_t)rc.x0 | ((uint32_t)rc.y0 << 16);
+    s_w[tid] = (float)(rc.x1 - rc.x0 + 1);
+    s_pu[tid] = r.pu;
+    s_pv[tid] = r.pv;
+    s_fa[tid] = -r.c00;
+    s_fb[tid] = -r.c01;
+    s_fc[tid] = -r.c11;
+    s_ia[tid] = -0.5f / r.c00;
+    s_ic[tid] = -0.5f / r.c11;
+    __syncthreads();
+    for (uint32_t e = (uint32_t)tid; e < total; e += kBlock) {
+      int j = 0;  // the last Gaussian whose offset is <= e (it has entries)
+#pragma unroll
+      for (int step = kBlock / 2; step > 0; step >>= 1)
+        if (s_off[j + step] <= e) j += step;
+      const uint32_t kin = e - s_off[j];
+      const float wf = s_w[j];
+      int ry = (int)__fdividef((float)kin, wf);  // row within the rectangle, corrected below
+      const int wi = (int)wf;
+      if ((uint32_t)((ry + 1) * wi) <= kin) ++ry;
+      if ((uint32_t)(ry * wi) > kin) --ry;
+      const int rx = (int)kin - ry * wi;
+      const uint32_t org = s_org[j];
+      const int tx = (int)(org & 0xffffu) + rx, ty = (int)(org >> 16) + ry;
+      const float pu = s_pu[j], pv = s_pv[j], fa = s_fa[j], fb = s_fb[j], fc = s_fc[j];
+      const float ia = s_ia[j], ic = s_ic[j];
+      uint32_t m = 0;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const int sx = tx * kTile + (w & 1) * kSub, sy = ty * kTile + (w >> 1) * kSub;
+        const float f = rect_min_form(fa, fb, fc, ia, ic, (float)sx - pu, (float)(sx + kSub - 1) - pu,
+                                      (float)sy - pv, (float)(sy + kSub - 1) - pv);
+        m |= (f <= a.qmax ? 1u : 0u) << w;
       }
+      const uint32_t pos = atomicAdd(&cur[ty * a.TX + tx], 1u);
+      if (pos < a.cap)
+        list[pos] = make_uint2((uint32_t)(gk + j) | (m << kEntryMaskShift), base + e);
+    }
     base += total;
+    __syncthreads();  // the next batch restages
   }
 }
 
@@ -254,9 +299,9 @@ void launch_proj_scatter(const ProjArgs &a, const Rec2 *rec, const uint32_t *his
 
 // One workgroup per (view, 16x16 tile); wave w owns the 8x8 sub-tile
 // (w & 1, w >> 1), one pixel per lane.  The tile's records are staged in LDS
-// in batches of 256.  For each chunk of 64 records, lane i tests record i
-// against the wave's sub-tile (exact minimum of the quadratic form over the
-// sub-tile) and, if it hits, rewrites it relative to the sub-tile centre as
+// in batches of 256.  For each chunk of 64 records, lane i takes record i if
+// its entry's mask marks the wave's sub-tile (set by the scatter) and
+// rewrites it relative to the sub-tile centre as
 //   q' + log2|rho_hat| = K0 + K1 x + K2 y + c00 x^2 + c01 x y + c11 y^2
 // (x, y: lane offsets from the centre), so that each kept record costs five
 // FMAs, one exp2 and a select per pixel.  The pixel sums sign(rho_hat)
@@ -267,10 +312,10 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
                                                        const uint32_t *__restrict__ tile_start,
                                                        float *__restrict__ image,
                                                        float *__restrict__ partial) {
-  // staged records: (pu, pv, c00, c01), (c11, rho, 1/(2a), 1/(2c)) with a = -c00,
-  // c = -c11 the positive form, and log2|rho|, computed once per workgroup
+  // staged records: (pu, pv, c00, c01), (c11, rho, log2|rho|, -) and the
+  // entry's sub-tile mask
   __shared__ float4 s_r0[kBlock], s_r1[kBlock];
-  __shared__ float s_lr[kBlock];
+  __shared__ uint8_t s_m[kBlock];
   // per wave: the kept records' coefficients, compacted, two float4 each
   __shared__ float4 s_k[4][64][2];
   const int wi = xcd_remap(blockIdx.x, gridDim.x);
@@ -283,7 +328,6 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
   const float cxs = (float)sx0 + 0.5f * (kSub - 1), cys = (float)sy0 + 0.5f * (kSub - 1);
   const float lx = (float)(lane & 7) - 0.5f * (kSub - 1), ly = (float)(lane >> 3) - 0.5f * (kSub - 1);
   const float lxx = lx * lx, lxy = lx * ly, lyy = ly * ly;
-  const float hs = 0.5f * (kSub - 1);
   uint32_t beg, end;
   list_part(min(tile_start[item], a.cap), min(tile_start[item + 1], a.cap), part, a.parts, beg,
             end);
@@ -294,27 +338,25 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
     const int n = (int)min((uint32_t)kBlock, end - base);
     __syncthreads();
     if (tid < n) {
-      const uint32_t g = list[base + tid].x;
-      const float4 *p = reinterpret_cast<const float4 *>(rv + g);
+      const uint32_t ex = list[base + tid].x;
+      const float4 *p = reinterpret_cast<const float4 *>(rv + (ex & kEntryIndexMask));
       const float4 r0 = p[0], r1 = p[1];
       s_r0[tid] = r0;
-      s_r1[tid] = make_float4(r1.x, r1.y, -0.5f / r0.z, -0.5f / r1.x);
-      s_lr[tid] = __log2f(fabsf(r1.y));
+      s_r1[tid] = make_float4(r1.x, r1.y, __log2f(fabsf(r1.y)), 0.f);
+      s_m[tid] = (uint8_t)(ex >> kEntryMaskShift);
     }
     __syncthreads();
     for (int c0 = 0; c0 < n; c0 += 64) {
       const int i = c0 + lane;
       bool hit = false;
       float4 k0, k1;
-      if (i < n) {
+      if (i < n && ((s_m[i] >> w) & 1u)) {
         const float4 r0 = s_r0[i], r1 = s_r1[i];
         const float c00 = r0.z, c01 = r0.w, c11 = r1.x, rho = r1.y;
         const float u = r0.x - cxs, vv = r0.y - cys;  // centre relative to the sub-tile centre
-        const float m = rect_min_form(-c00, -c01, -c11, r1.z, r1.w, -hs - u, hs - u, -hs - vv,
-                                      hs - vv);
-        hit = m <= a.qmax && rho != 0.f;
+        hit = rho != 0.f;
         if (hit) {
-          const float lr = s_lr[i];
+          const float lr = r1.z;
           const float K0 = u * (c00 * u + c01 * vv) + c11 * vv * vv + lr;
           const float K1 = -(2.f * c00 * u + c01 * vv);
           const float K2 = -(c01 * u + 2.f * c11 * vv);
@@ -416,7 +458,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *_
                                                        const float *__restrict__ grad_image,
                                                        float *__restrict__ slots) {
   __shared__ float s_pu[kBlock], s_pv[kBlock], s_c00[kBlock], s_c01[kBlock], s_c11[kBlock];
-  __shared__ float s_ia[kBlock], s_ic[kBlock];
+  __shared__ uint8_t s_m[kBlock];
   __shared__ __align__(16) float s_G[kTile * kTile];
   __shared__ float s_acc[4][6][kBlock];
   __shared__ uint16_t s_q[4][kBlock];
@@ -449,19 +491,19 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *_
     if (tid < n) {
       const uint2 ent = list[base + tid];
       my_slot = ent.y;
-      const float4 *p = reinterpret_cast<const float4 *>(rv + ent.x);
+      const float4 *p = reinterpret_cast<const float4 *>(rv + (ent.x & kEntryIndexMask));
       float4 q0 = p[0], q1 = p[1];
       s_pu[tid] = q0.x; s_pv[tid] = q0.y; s_c00[tid] = q0.z; s_c01[tid] = q0.w;
       s_c11[tid] = q1.x;
-      s_ia[tid] = -0.5f / q0.z;
-      s_ic[tid] = -0.5f / q1.x;
+      s_m[tid] = (uint8_t)(ent.x >> kEntryMaskShift);
     }
 #pragma unroll
     for (int k = 0; k < 6; ++k)
 #pragma unroll
       for (int ww = 0; ww < 4; ++ww) s_acc[ww][k][tid] = 0.f;
     __syncthreads();
-    // Compact the records that meet this wave's sub-tile into two queues.
+    // Compact the records whose entry mask marks this wave's sub-tile (the
+    // cutoff ellipse meets it; set by the scatter) into two queues.
     // Entries whose form stays below kChainRange over the whole sub-tile
     // (its maximum is at a corner) go to the front: their walk steps
     // e = exp2(q) by multiplication, along a row by r = exp2(q(x+1) - q(x)),
@@ -474,12 +516,11 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *_
     for (int c0 = 0; c0 < n; c0 += 64) {
       const int i = c0 + lane;
       bool hit = false, steep = false;
-      if (i < n) {
+      if (i < n && ((s_m[i] >> w) & 1u)) {
         const float pu = s_pu[i], pv = s_pv[i];
         const float fa = -s_c00[i], fb = -s_c01[i], fc = -s_c11[i];
         const float x0 = rx0 - pu, x1 = rx1 - pu, y0 = ry0 - pv, y1 = ry1 - pv;
-        float m = rect_min_form(fa, fb, fc, s_ia[i], s_ic[i], x0, x1, y0, y1);
-        hit = m <= a.qmax;
+        hit = true;
         const float ax0 = fa * x0 * x0, ax1 = fa * x1 * x1, cy0 = fc * y0 * y0, cy1 = fc * y1 * y1;
         const float fmax = fmaxf(fmaxf(fmaf(fb * x0, y0, ax0 + cy0), fmaf(fb * x1, y0, ax1 + cy0)),
                                  fmaxf(fmaf(fb * x0, y1, ax0 + cy1), fmaf(fb * x1, y1, ax1 + cy1)));
