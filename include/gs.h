@@ -206,7 +206,7 @@ GS_API gs_status gs_voxelize_bwd(const gs_gaussians *g, const gs_grid *grid, flo
  * window (sigma 1.5, normalised), zero padding, C1 = 0.01^2, C2 = 0.03^2.
  * loss_out (device, 3 floats): {total, l1, ssim}.
  * grad (device [n_img][h][w], may be NULL): d total / d render, overwritten.
- * plan must not be NULL (holds the partial sums and SSIM coefficient maps). */
+ * plan must not be NULL (holds the per-tile partial sums). */
 GS_API gs_status gs_loss_image(const float *render, const float *measured, int32_t n_img, int32_t h,
                         int32_t w, float lambda_ssim, float *loss_out, float *grad, gs_plan *plan,
                         hipStream_t stream);

@@ -661,7 +661,6 @@ gs_status gs_plan_reserve(gs_plan *p, const gs_reserve *r, hipStream_t s) {
     GS_TRY(ensure(p, p->p_part, 72 * (size_t)proj_chain_chunks((int)V) * (size_t)M, s));
     // render parts x tiles stays below 8192 + tiles
     GS_TRY(ensure(p, p->p_fpart, 4 * (size_t)kBlock * (size_t)(8192 + VT), s));
-    GS_TRY(ensure(p, p->l_coef, 12 * (size_t)V * r->width * r->height, s));
     GS_TRY(ensure(p, p->l_part, 8 * (size_t)ssim_num_blocks((int)V, r->height, r->width), s));
     for (int k = 0; k < gs_plan::kStageRing; ++k) {
       const size_t bytes = sizeof(DevView) * (size_t)V;
@@ -975,16 +974,15 @@ gs_status gs_loss_image(const float *render, const float *measured, int32_t n_im
   if (!plan) return fail(GS_EINVAL, "plan is NULL");
   plan->used = true;
   plan->last_stream = stream;
-  const size_t N = (size_t)n_img * h * w;
   const int nb = ssim_num_blocks(n_img, h, w);
-  GS_TRY(ensure(plan, plan->l_coef, 3 * sizeof(float) * N, stream));
   GS_TRY(ensure(plan, plan->l_part, 2 * sizeof(float) * (size_t)nb, stream));
   StageTimer t(plan, GS_STAGE_LOSS_IMAGE, stream);
-  launch_ssim_coeffs(render, measured, n_img, h, w, P<float>(plan->l_coef), P<float>(plan->l_part),
-                     stream);
-  launch_loss_finish(P<float>(plan->l_part), nb, n_img, h, w, lambda_ssim, loss_out, stream);
   if (grad)
-    launch_ssim_grad(render, measured, P<float>(plan->l_coef), n_img, h, w, lambda_ssim, grad, stream);
+    launch_ssim_fused(render, measured, n_img, h, w, lambda_ssim, grad, P<float>(plan->l_part),
+                      stream);
+  else
+    launch_ssim_coeffs(render, measured, n_img, h, w, nullptr, P<float>(plan->l_part), stream);
+  launch_loss_finish(P<float>(plan->l_part), nb, n_img, h, w, lambda_ssim, loss_out, stream);
   return check_launch("image loss");
 }
 

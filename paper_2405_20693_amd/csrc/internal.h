@@ -368,10 +368,10 @@ void launch_vox_chain(const VoxArgs &a, const Rec3 *rec, const uint32_t *offsets
 
 void launch_ssim_coeffs(const float *x, const float *y, int n, int h, int w, float *coef,
                         float *partials, hipStream_t s);
-void launch_ssim_grad(const float *x, const float *y, const float *coef, int n, int h, int w,
-                      float lambda_ssim, float *grad, hipStream_t s);
 void launch_loss_finish(const float *partials, int n_part, int n, int h, int w, float lambda_ssim,
                         float *loss_out, hipStream_t s);
+void launch_ssim_fused(const float *x, const float *y, int n, int h, int w, float lambda_ssim,
+                       float *grad, float *partials, hipStream_t s);
 int ssim_num_blocks(int n, int h, int w);
 void launch_tv(const float *vol, int nx, int ny, int nz, float weight, float *grad, int accumulate,
                float *partials, int *n_part, hipStream_t s);

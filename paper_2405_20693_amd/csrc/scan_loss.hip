@@ -153,29 +153,6 @@ int ssim_num_blocks(int n, int h, int w) {
   return n * ((h + kSH - 1) / kSH) * ((w + kSW - 1) / kSW);
 }
 
-// Row pass of Q planes: out[q][r][c] = sum_k w_k in[q][r][c + k], for the
-// kIH rows and kSW output columns; 4 columns per task.
-template <int Q>
-__device__ inline void row_pass(const float (*in)[kIH][kIW], float (*out)[kIH][kSW]) {
-  constexpr int tasks = kIH * (kSW / kRB);
-  for (int task = threadIdx.x; task < tasks; task += kBlock) {
-    const int r = task / (kSW / kRB), c0 = (task - r * (kSW / kRB)) * kRB;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      float win[kRB + kWin - 1];
-#pragma unroll
-      for (int k = 0; k < kRB + kWin - 1; ++k) win[k] = in[q][r][c0 + k];
-#pragma unroll
-      for (int o = 0; o < kRB; ++o) {
-        float acc = 0.f;
-#pragma unroll
-        for (int k = 0; k < kWin; ++k) acc = fmaf(c_win[k], win[o + k], acc);
-        out[q][r][c0 + o] = acc;
-      }
-    }
-  }
-}
-
 // Column pass: 4 consecutive output rows of one column per thread (256 tasks).
 template <int Q>
 __device__ inline void col_pass(const float (*hz)[kIH][kSW], float (*m)[kRB]) {
@@ -198,7 +175,7 @@ __device__ inline void col_pass(const float (*hz)[kIH][kSW], float (*m)[kRB]) {
 // Computes the per-pixel SSIM map and the coefficient maps
 //   D1 = dS/dmu_x - 2 mu_x dS/dsxx - mu_y dS/dsxy,  D2 = dS/dsxx,  D3 = dS/dsxy
 // so that d mean(S) / d x = (blur(D1) + 2 x blur(D2) + y blur(D3)) / N.
-// coef: [3][n][h][w].  partials[block] = {sum S, sum |x - y|}.
+// coef: [3][n][h][w] (may be NULL).  partials[block] = {sum S, sum |x - y|}.
 __global__ __launch_bounds__(kBlock) void k_ssim_coeffs(const float *__restrict__ x,
                                                         const float *__restrict__ y, int n, int h,
                                                         int w, float *__restrict__ coef,
@@ -268,9 +245,11 @@ __global__ __launch_bounds__(kBlock) void k_ssim_coeffs(const float *__restrict_
     const float dsxx = -S / B2;
     const float dsxy = 2.f * A1 * iB;
     const int64_t off = (int64_t)img * h * w + (int64_t)gy * w + gx;
-    coef[off] = dmx - 2.f * mx * dsxx - my * dsxy;
-    coef[N + off] = dsxx;
-    coef[2 * N + off] = dsxy;
+    if (coef) {
+      coef[off] = dmx - 2.f * mx * dsxx - my * dsxy;
+      coef[N + off] = dsxx;
+      coef[2 * N + off] = dsxy;
+    }
     ssum += S;
     lsum += fabsf(sin_[0][r0 + o + kR][c + kR] - sin_[1][r0 + o + kR][c + kR]);
   }
@@ -297,53 +276,185 @@ void launch_ssim_coeffs(const float *x, const float *y, int n, int h, int w, flo
                      w, coef, partials);
 }
 
-// grad = sign(x - y) / N - lambda (blur(D1) + 2 x blur(D2) + y blur(D3)) / N
-__global__ __launch_bounds__(kBlock) void k_ssim_grad(const float *__restrict__ x,
-                                                      const float *__restrict__ y,
-                                                      const float *__restrict__ coef, int n, int h,
-                                                      int w, float lambda, float *__restrict__ grad) {
-  __shared__ float sd[3][kIH][kIW];
-  __shared__ float hz[3][kIH][kSW];
+// Loss and gradient in one pass per 32 x 32 output tile.  The gradient at a
+// pixel needs the coefficient maps D1..D3 on a 5-pixel halo, and those need
+// the inputs on a further 5-pixel halo, so the workgroup stages x and y over
+// 52 x 52, computes the five blurred moments and D1..D3 over the 42 x 42
+// coefficient region (zero outside the image: the maps are only defined on
+// image pixels), then blurs the coefficients for its 32 x 32 outputs.  Each
+// plane is blurred separately (row pass to LDS, column pass to registers) to
+// keep LDS at about 32 KB; the coefficient maps overwrite the staged inputs.
+// grad = (sign(x - y) - lambda (blur(D1) + 2 x blur(D2) + y blur(D3))) / N;
+// partials[block] = {sum S, sum |x - y|} over the tile's image pixels.
+constexpr int kDW = kSW + 2 * kR;  // 42: coefficient region edge
+constexpr int kXW = kDW + 2 * kR;  // 52: input region edge
+constexpr int kF1 = 7;             // stage 1: outputs per row task and per column task
+constexpr int kF2 = 8;             // stage 2: outputs per row task
+
+__global__ __launch_bounds__(kBlock) void k_ssim_fused(const float *__restrict__ x,
+                                                       const float *__restrict__ y, int n, int h,
+                                                       int w, float lambda,
+                                                       float *__restrict__ grad,
+                                                       float *__restrict__ partials) {
+  __shared__ float s_in[2 * kXW * kXW];  // x, y over 52 x 52; later D1..D3 over 42 x 42
+  __shared__ float s_h[kXW * kDW];       // row-pass output of one plane
+  __shared__ float red[2][kBlock];
+  static_assert(3 * kDW * kDW <= 2 * kXW * kXW, "the coefficient maps fit the input buffer");
+  float *sx = s_in, *sy = s_in + kXW * kXW;
   const int tiles_x = (w + kSW - 1) / kSW, tiles_y = (h + kSH - 1) / kSH;
   const int b = blockIdx.x;
   const int img = b / (tiles_x * tiles_y), tt = b - img * tiles_x * tiles_y;
   const int ty = tt / tiles_x, tx = tt - ty * tiles_x;
-  const int X0 = tx * kSW - kR, Y0 = ty * kSH - kR;
-  const int64_t N = (int64_t)n * h * w;
+  const int X0 = tx * kSW, Y0 = ty * kSH;  // first output pixel
   const int64_t ib = (int64_t)img * h * w;
   const int tid = threadIdx.x;
-  for (int i = tid; i < kIW * kIH; i += kBlock) {
-    const int r = i / kIW, c = i - r * kIW;
-    const int gy = Y0 + r, gx = X0 + c;
+  for (int i = tid; i < kXW * kXW; i += kBlock) {
+    const int r = i / kXW, c = i - r * kXW;
+    const int gy = Y0 - 2 * kR + r, gx = X0 - 2 * kR + c;
     const bool in = gx >= 0 && gx < w && gy >= 0 && gy < h;
-    const int64_t o = ib + (int64_t)gy * w + gx;
-    for (int q = 0; q < 3; ++q) sd[q][r][c] = in ? coef[q * N + o] : 0.f;
+    sx[i] = in ? x[ib + (int64_t)gy * w + gx] : 0.f;
+    sy[i] = in ? y[ib + (int64_t)gy * w + gx] : 0.f;
   }
   __syncthreads();
-  row_pass<3>(sd, hz);
-  __syncthreads();
-  float m[3][kRB];
-  col_pass<3>(hz, m);
-  const int c = tid & (kSW - 1), r0 = (tid / kSW) * kRB;
-  const float invN = 1.f / (float)N;
+  // stage 1: blurred x, y, x^2, y^2, xy at the thread's 7 coefficient positions
+  // (column dc, rows dr0 .. dr0 + 6 of the 42 x 42 region; 252 threads)
+  const bool t1 = tid < (kDW / kF1) * kDW;
+  const int dc = tid % kDW, dr0 = (tid / kDW) * kF1;
+  float m[5][kF1];
 #pragma unroll
-  for (int o = 0; o < kRB; ++o) {
-    const int gy = ty * kSH + r0 + o, gx = tx * kSW + c;
-    if (gx >= w || gy >= h) continue;
-    const int64_t off = ib + (int64_t)gy * w + gx;
-    const float xv = x[off], yv = y[off];
-    const float dssim = m[0][o] + 2.f * xv * m[1][o] + yv * m[2][o];
-    const float d = xv - yv;
-    const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
-    grad[off] = (sg - lambda * dssim) * invN;
+  for (int q = 0; q < 5; ++q) {
+    for (int task = tid; task < kXW * (kDW / kF1); task += kBlock) {
+      const int r = task / (kDW / kF1), c0 = (task - r * (kDW / kF1)) * kF1;
+      float win[kF1 + kWin - 1];
+#pragma unroll
+      for (int k = 0; k < kF1 + kWin - 1; ++k) {
+        const float xv = sx[r * kXW + c0 + k], yv = sy[r * kXW + c0 + k];
+        win[k] = q == 0 ? xv : q == 1 ? yv : q == 2 ? xv * xv : q == 3 ? yv * yv : xv * yv;
+      }
+#pragma unroll
+      for (int o = 0; o < kF1; ++o) {
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < kWin; ++k) acc = fmaf(c_win[k], win[o + k], acc);
+        s_h[r * kDW + c0 + o] = acc;
+      }
+    }
+    __syncthreads();
+    if (t1) {
+      float win[kF1 + kWin - 1];
+#pragma unroll
+      for (int k = 0; k < kF1 + kWin - 1; ++k) win[k] = s_h[(dr0 + k) * kDW + dc];
+#pragma unroll
+      for (int o = 0; o < kF1; ++o) {
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < kWin; ++k) acc = fmaf(c_win[k], win[o + k], acc);
+        m[q][o] = acc;
+      }
+    }
+    __syncthreads();
+  }
+  // SSIM, its derivative maps, and the tile's sums (interior positions only)
+  float ssum = 0.f, lsum = 0.f;
+  float dv[3][kF1];
+#pragma unroll
+  for (int o = 0; o < kF1; ++o) {
+    dv[0][o] = dv[1][o] = dv[2][o] = 0.f;
+    const int dr = dr0 + o;
+    const int gy = Y0 - kR + dr, gx = X0 - kR + dc;
+    if (!t1 || gx < 0 || gx >= w || gy < 0 || gy >= h) continue;
+    const float mx = m[0][o], my = m[1][o];
+    const float sxx = m[2][o] - mx * mx, syy = m[3][o] - my * my, sxy = m[4][o] - mx * my;
+    const float A1 = 2.f * mx * my + kC1, A2 = 2.f * sxy + kC2;
+    const float B1 = mx * mx + my * my + kC1, B2 = sxx + syy + kC2;
+    const float iB = 1.f / (B1 * B2);
+    const float S = A1 * A2 * iB;
+    const float dmx = 2.f * my * A2 * iB - 2.f * mx * S / B1;
+    const float dsxx = -S / B2;
+    const float dsxy = 2.f * A1 * iB;
+    dv[0][o] = dmx - 2.f * mx * dsxx - my * dsxy;
+    dv[1][o] = dsxx;
+    dv[2][o] = dsxy;
+    if (dr >= kR && dr < kR + kSH && dc >= kR && dc < kR + kSW) {
+      ssum += S;
+      const int i = (dr + kR) * kXW + dc + kR;
+      lsum += fabsf(sx[i] - sy[i]);
+    }
+  }
+  red[0][tid] = ssum;
+  red[1][tid] = lsum;
+  __syncthreads();  // the staged inputs are no longer read
+  if (grad) {
+    if (t1) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int o = 0; o < kF1; ++o) s_in[(q * kDW + dr0 + o) * kDW + dc] = dv[q][o];
+    }
+    __syncthreads();
+    // stage 2: blurred D1..D3 at 4 outputs per thread (column c, rows r0 .. r0 + 3)
+    const int c = tid & (kSW - 1), r0 = (tid / kSW) * kRB;
+    float bd[3][kRB];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const float *D = s_in + q * kDW * kDW;
+      for (int task = tid; task < kDW * (kSW / kF2); task += kBlock) {
+        const int r = task / (kSW / kF2), c0 = (task - r * (kSW / kF2)) * kF2;
+        float win[kF2 + kWin - 1];
+#pragma unroll
+        for (int k = 0; k < kF2 + kWin - 1; ++k) win[k] = D[r * kDW + c0 + k];
+#pragma unroll
+        for (int o = 0; o < kF2; ++o) {
+          float acc = 0.f;
+#pragma unroll
+          for (int k = 0; k < kWin; ++k) acc = fmaf(c_win[k], win[o + k], acc);
+          s_h[r * kSW + c0 + o] = acc;
+        }
+      }
+      __syncthreads();
+      float win[kRB + kWin - 1];
+#pragma unroll
+      for (int k = 0; k < kRB + kWin - 1; ++k) win[k] = s_h[(r0 + k) * kSW + c];
+#pragma unroll
+      for (int o = 0; o < kRB; ++o) {
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < kWin; ++k) acc = fmaf(c_win[k], win[o + k], acc);
+        bd[q][o] = acc;
+      }
+      __syncthreads();
+    }
+    const float invN = 1.f / (float)((int64_t)n * h * w);
+#pragma unroll
+    for (int o = 0; o < kRB; ++o) {
+      const int gy = Y0 + r0 + o, gx = X0 + c;
+      if (gx >= w || gy >= h) continue;
+      const int64_t off = ib + (int64_t)gy * w + gx;
+      const float xv = x[off], yv = y[off];
+      const float dssim = bd[0][o] + 2.f * xv * bd[1][o] + yv * bd[2][o];
+      const float d = xv - yv;
+      const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
+      grad[off] = (sg - lambda * dssim) * invN;
+    }
+  }
+  for (int d = kBlock / 2; d > 0; d >>= 1) {
+    if (tid < d) {
+      red[0][tid] += red[0][tid + d];
+      red[1][tid] += red[1][tid + d];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    partials[2 * b] = red[0][0];
+    partials[2 * b + 1] = red[1][0];
   }
 }
 
-void launch_ssim_grad(const float *x, const float *y, const float *coef, int n, int h, int w,
-                      float lambda_ssim, float *grad, hipStream_t s) {
+void launch_ssim_fused(const float *x, const float *y, int n, int h, int w, float lambda_ssim,
+                       float *grad, float *partials, hipStream_t s) {
   init_window();
-  hipLaunchKernelGGL(k_ssim_grad, dim3(ssim_num_blocks(n, h, w)), dim3(kBlock), 0, s, x, y, coef, n,
-                     h, w, lambda_ssim, grad);
+  hipLaunchKernelGGL(k_ssim_fused, dim3(ssim_num_blocks(n, h, w)), dim3(kBlock), 0, s, x, y, n, h,
+                     w, lambda_ssim, grad, partials);
 }
 
 // Sums the per-block partials in double, in a fixed order.
