@@ -407,7 +407,7 @@ gs_status proj_bin(gs_plan *pl, const gs_gaussians *g, const gs_view *views, int
   unsigned long long entries;
   if (pl->reserved) {
     // no readback: the scatter keeps what the reserved list and slots hold
-    entries = std::min(pl->p_list.cap / 8, pl->p_slots.cap / 24);
+    entries = std::min(pl->p_list.cap / 8, pl->p_slots.cap >= 16 ? (pl->p_slots.cap - 16) / 24 : 0);
     entries = std::min<unsigned long long>(entries, 0xffffffffull);
   } else {
     if (hipMemcpyAsync(pl->readback, pl->p_totals.p, 16, hipMemcpyDeviceToHost, s) != hipSuccess)
@@ -657,7 +657,7 @@ gs_status gs_plan_reserve(gs_plan *p, const gs_reserve *r, hipStream_t s) {
     GS_TRY(ensure(p, p->p_totals, 16, s));
     GS_TRY(ensure(p, p->p_scan_tmp, 4 * (size_t)(2 * ((VT + 4095) / 4096) + 2 * ((VC + 4095) / 4096) + 2), s));
     GS_TRY(ensure(p, p->p_list, 8 * (size_t)std::max<int64_t>(E, 1), s));
-    GS_TRY(ensure(p, p->p_slots, 24 * (size_t)std::max<int64_t>(E, 1), s));
+    GS_TRY(ensure(p, p->p_slots, 24 * (size_t)std::max<int64_t>(E, 1) + 16, s));
     GS_TRY(ensure(p, p->p_part, 72 * (size_t)proj_chain_chunks((int)V) * (size_t)M, s));
     // render parts x tiles stays below 8192 + tiles
     GS_TRY(ensure(p, p->p_fpart, 4 * (size_t)kBlock * (size_t)(8192 + VT), s));
@@ -862,7 +862,7 @@ static gs_status project_bwd(const gs_gaussians *g, const gs_view *views, int32_
   if (!same_proj(plan, g, views, n_views, cutoff))
     GS_TRY(proj_bin(plan, g, views, n_views, cutoff, stream));
   const ProjArgs &a = plan->pargs;
-  GS_TRY(ensure(plan, plan->p_slots, 24 * (size_t)plan->p_entries, stream));
+  GS_TRY(ensure(plan, plan->p_slots, 24 * (size_t)plan->p_entries + 16, stream));
   GS_TRY(ensure(plan, plan->p_part, 72 * (size_t)proj_chain_chunks(a.V) * (size_t)a.M, stream));
   {
     StageTimer t(plan, GS_STAGE_RENDER_BWD, stream);

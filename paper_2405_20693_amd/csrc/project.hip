@@ -664,33 +664,85 @@ void launch_render_bwd(const ProjArgs &a, const Rec2 *rec, const uint2 *list,
 constexpr int kChainViews = 8;
 constexpr int kChainParts = 16;  // gradient parts; +2 with statistics (NDC norm sum, views)
 
+// A wave's 64 consecutive Gaussians own one contiguous run of slots per view
+// (offsets follow Gaussian order), so the wave stages that run in LDS with
+// 16-byte loads and each lane then sums its own slots from LDS; runs longer
+// than the staging buffer are read directly.  The slot buffer carries 16
+// bytes of padding for the rounded-up last load.
+constexpr int kChainStage = 512;  // float4 per wave (8 KB)
+
 __global__ __launch_bounds__(kBlock) void k_proj_chain(ProjArgs a, const Rec2 *__restrict__ rec,
                                                        const uint32_t *__restrict__ offsets,
                                                        const float *__restrict__ slots,
                                                        float *__restrict__ part, int stats) {
+  __shared__ float4 s_st[4][kChainStage];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (g >= a.M) return;
+  const bool active = g < a.M;
   const int vc = blockIdx.y;
   const int n_parts = kChainParts + (stats ? 2 : 0);
   float ndc_sum = 0.f, n_vis = 0.f;
   Gauss G;
-  load_gauss(a.mean, a.scale, a.quat, a.dens, g, G);
+  G.ok = false;
+  if (active) load_gauss(a.mean, a.scale, a.quat, a.dens, g, G);
   float gp[3] = {0.f, 0.f, 0.f}, gs[3] = {0.f, 0.f, 0.f}, gR[9] = {0.f};
   float grho = 0.f;
   const int v0 = vc * kChainViews, v1 = min(v0 + kChainViews, a.V);
-  if (G.ok) {
+  const float4 *slots4 = reinterpret_cast<const float4 *>(slots);
+  {
+    // the next view's tile rectangle and slot offset are loaded one view ahead
+    uint2 rw_next = make_uint2(1u, 0u);
+    uint32_t off_next = 0;
+    if (G.ok && v0 < v1) {
+      const int64_t vg = (int64_t)v0 * a.M + g;
+      rw_next = make_uint2(rec[vg].r0, rec[vg].r1);
+      off_next = offsets[vg];
+    }
     for (int v = v0; v < v1; ++v) {
-      const int64_t vg = (int64_t)v * a.M + g;
-      const Rec2 r = rec[vg];
-      const Rect2 rc = unpack_rect(r.r0, r.r1);
-      const int cnt = rect_count(rc);
-      const uint32_t off = offsets[vg];
-      if (!cnt || (uint64_t)off + (uint64_t)cnt > a.cap) continue;  // (beyond capacity: dropped)
-      const float *sl = slots + (int64_t)off * 6;
-      float S[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      for (int k = 0; k < cnt; ++k)
+      int cnt = 0;
+      uint32_t off = 0;
+      if (G.ok) {
+        cnt = rect_count(unpack_rect(rw_next.x, rw_next.y));
+        off = off_next;
+        if ((uint64_t)off + (uint64_t)cnt > a.cap) cnt = 0;  // (beyond capacity: dropped)
+        if (v + 1 < v1) {
+          const int64_t vg = (int64_t)(v + 1) * a.M + g;
+          rw_next = make_uint2(rec[vg].r0, rec[vg].r1);
+          off_next = offsets[vg];
+        }
+      }
+      const uint64_t have = __ballot(cnt > 0);
+      if (!have) continue;
+      const int fl = __builtin_ctzll(have), ll = 63 - __builtin_clzll(have);
+      const uint32_t lo = (uint32_t)__shfl((int)off, fl);
+      const uint32_t hi = (uint32_t)__shfl((int)(off + (uint32_t)cnt), ll);
+      const uint64_t b4 = ((uint64_t)lo * 6u) >> 2, e4 = ((uint64_t)hi * 6u + 3u) >> 2;
+      const bool staged = e4 - b4 <= (uint64_t)kChainStage;
+      if (staged) {
+        const int n4 = (int)(e4 - b4);
 #pragma unroll
-        for (int j = 0; j < 6; ++j) S[j] += sl[6 * k + j];
+        for (int it = 0; it < kChainStage / 64; ++it) {
+          const int i = it * 64 + lane;
+          if (i < n4) s_st[w][i] = slots4[b4 + i];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+      float S[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      if (cnt && staged) {
+        const float *sl = reinterpret_cast<const float *>(s_st[w]) + ((uint64_t)off * 6u - b4 * 4u);
+        for (int k = 0; k < cnt; ++k)
+#pragma unroll
+          for (int j = 0; j < 6; ++j) S[j] += sl[6 * k + j];
+      } else if (cnt) {
+        const float *sl = slots + (int64_t)off * 6;
+        for (int k = 0; k < cnt; ++k)
+#pragma unroll
+          for (int j = 0; j < 6; ++j) S[j] += sl[6 * k + j];
+      }
+      __builtin_amdgcn_wave_barrier();  // the next view restages
+      if (!cnt) continue;
       const DevView V = a.views[v];
       Proj2 P;
       project_one(G, V, P);
@@ -779,6 +831,7 @@ __global__ __launch_bounds__(kBlock) void k_proj_chain(ProjArgs a, const Rec2 *_
       for (int i = 0; i < 3; ++i) gp[i] += W[i] * gt[0] + W[3 + i] * gt[1] + W[6 + i] * gt[2];
     }
   }
+  if (!active) return;
   float *o = part + (int64_t)vc * n_parts * a.M + g;
   for (int i = 0; i < 3; ++i) o[(int64_t)i * a.M] = gp[i];
   for (int i = 0; i < 3; ++i) o[(int64_t)(3 + i) * a.M] = gs[i];
