@@ -230,6 +230,12 @@ __device__ inline void project_one(const Gauss &G, const DevView &V, Proj2 &P) {
 // to be the centre).  So only the facing x edge and the facing y edge are
 // searched; where no x (y) edge faces the centre, the other axis' edge holds
 // the minimum and the extra candidate is just some point of the rectangle.
+// Number of set bits of `mask` below the calling lane.
+__device__ inline int lanes_below(uint64_t mask) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
 // Tile-list entry (Gaussian index | sub-tile mask << kEntryMaskShift, backward
 // slot): bit w of the mask is set when the cutoff ellipse meets 8x8 sub-tile w
 // of the 16x16 tile (w = (x half) + 2 (y half)).

@@ -36,12 +36,6 @@ __device__ inline uint32_t block_sum(uint32_t x, uint32_t *sh4) {
   return t;
 }
 
-// Number of set bits of `mask` below the calling lane.
-__device__ inline int lanes_below(uint64_t mask) {
-  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
 // --------------------------------------------------------- projection ----
 
 // Record (pixel units) and tile rectangle of one projected Gaussian.

@@ -326,6 +326,37 @@ void launch_vox_fwd(const VoxArgs &a, const Rec3 *rec, const uint32_t *list,
 // Lanes are (record, sub-cube) pairs; each walks the sub-cube's 64 voxels and
 // accumulates 10 moments of H e (e = exp2(q')): 1, d_i, d_i d_j (index units,
 // d = voxel - centre).  Per-wave LDS accumulators, summed in fixed order.
+// Pairs whose form stays below kVChainRange over the sub-cube (its maximum is
+// at a corner) step e by multiplication: along x by r = exp2(q(x+1) - q(x)),
+// r by exp2(2 c00), and likewise down y and z, so ten exp2 per walk replace
+// 64 and every chained value stays a normal FP32 number; the others evaluate
+// exp2(q') per voxel.  The two kinds are queued apart (each pair's path is
+// its own).  Moments are summed per x column first (dx is constant down a
+// column) and combined once per walk.
+constexpr float kVChainRange = 120.f;
+
+__device__ inline float vox_form_max(const float (*s)[kBlock], int i, float x0, float y0,
+                                     float z0) {
+  // maximum over the 8 corners of the positive form -q' (convex)
+  const float e = (float)(kVSub - 1);
+  const float c00 = -s[3][i], c01 = -s[4][i], c02 = -s[5][i], c11 = -s[6][i], c12 = -s[7][i],
+              c22 = -s[8][i];
+  const float xs[2] = {x0 - s[0][i], x0 + e - s[0][i]};
+  const float ys[2] = {y0 - s[1][i], y0 + e - s[1][i]};
+  const float zs[2] = {z0 - s[2][i], z0 + e - s[2][i]};
+  float m = 0.f;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const float dx = xs[a], dy = ys[b], dz = zs[c];
+        m = fmaxf(m, dx * (c00 * dx + c01 * dy + c02 * dz) + dy * (c11 * dy + c12 * dz) +
+                         c22 * dz * dz);
+      }
+  return m;
+}
 __global__ __launch_bounds__(kBlock) void k_vox_bwd(VoxArgs a, const Rec3 *__restrict__ rec,
                                                     const uint32_t *__restrict__ list,
                                                     const uint32_t *__restrict__ tile_start,
@@ -333,7 +364,7 @@ __global__ __launch_bounds__(kBlock) void k_vox_bwd(VoxArgs a, const Rec3 *__res
                                                     const float *__restrict__ grad_vol,
                                                     float *__restrict__ slots) {
   __shared__ float s[13][kBlock];
-  __shared__ float s_H[kVTile * kVTile * kVTile];
+  __shared__ __align__(16) float s_H[kVTile * kVTile * kVTile];
   __shared__ float s_acc[4][10][kBlock];
   __shared__ uint16_t s_q[4][kBlock];
   const int wi = xcd_remap(blockIdx.x, gridDim.x);
@@ -349,6 +380,7 @@ __global__ __launch_bounds__(kBlock) void k_vox_bwd(VoxArgs a, const Rec3 *__res
   uint32_t beg, end;
   list_part(min(tile_start[item], a.cap), min(tile_start[item + 1], a.cap), part, a.bparts, beg,
             end);
+  const float ethr = __builtin_amdgcn_exp2f(a.thr);  // the cutoff on e = exp2(q')
   for (uint32_t base = beg; base < end; base += kBlock) {
     const int n = (int)min((uint32_t)kBlock, end - base);
     __syncthreads();
@@ -369,54 +401,119 @@ __global__ __launch_bounds__(kBlock) void k_vox_bwd(VoxArgs a, const Rec3 *__res
       const int lx0 = (sc & 1) * kVSub, ly0 = ((sc >> 1) & 1) * kVSub, lz0 = (sc >> 2) * kVSub;
       const float ox = (float)(T.tx * kVTile + lx0), oy = (float)(T.ty * kVTile + ly0),
                   oz = (float)(T.tz * kVTile + lz0);
-      int qn = 0;
+      int qn = 0, qs = 0;
       for (int c0 = 0; c0 < n; c0 += 64) {
         const int i = c0 + lane;
         const bool hit = (i < n) && box_hits(s, i, ox, oy, oz) && box_may_reach(s, i, ox, oy, oz, a.thr);
-        uint64_t mask = __ballot(hit);
-        if (hit)
-          s_q[w][qn + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u))] =
-              (uint16_t)i;
-        qn += __popcll(mask);
+        const bool steep = hit && !(vox_form_max(s, i, ox, oy, oz) <= kVChainRange);
+        const uint64_t mc = __ballot(hit && !steep), ms = __ballot(steep);
+        if (hit && !steep) s_q[w][qn + lanes_below(mc)] = (uint16_t)i;
+        if (steep) s_q[w][kBlock - 1 - (qs + lanes_below(ms))] = (uint16_t)i;
+        qn += __popcll(mc);
+        qs += __popcll(ms);
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      for (int qb = 0; qb < qn; qb += 64) {
-        const int j = qb + lane;
-        const bool active = j < qn;
-        const int e = active ? (int)s_q[w][j] : 0;
-        float m[10];
-        for (int k = 0; k < 10; ++k) m[k] = 0.f;
-        const float cx = s[0][e], cy = s[1][e], cz = s[2][e];
-        for (int z = 0; z < kVSub; ++z) {
-          const float dz = oz + (float)z - cz;
-          for (int y = 0; y < kVSub; ++y) {
-            const float dy = oy + (float)y - cy;
-            const float *Hrow = s_H + ((lz0 + z) * kVTile + (ly0 + y)) * kVTile + lx0;
+      for (int pass = 0; pass < 2; ++pass) {
+        const bool chain = pass == 0;
+        const int cnt = chain ? qn : qs;
+        for (int qb = 0; qb < cnt; qb += 64) {
+          const int j = qb + lane;
+          const bool active = j < cnt;
+          const int e = active ? (int)s_q[w][chain ? j : kBlock - 1 - j] : 0;
+          const float cx = s[0][e], cy = s[1][e], cz = s[2][e];
+          const float c00 = s[3][e], c01 = s[4][e], c02 = s[5][e], c11 = s[6][e], c12 = s[7][e],
+                      c22 = s[8][e];
+          const float dx0 = ox - cx, dy0 = oy - cy, dz0 = oz - cz;
+          // per x column: sums of H e times 1, dy, dz, dy^2, dy dz, dz^2
+          float C0[kVSub], Cy[kVSub], Cz[kVSub], Cyy[kVSub], Cyz[kVSub], Czz[kVSub];
 #pragma unroll
-            for (int x = 0; x < kVSub; ++x) {
-              const float dx = ox + (float)x - cx;
-              const float q = vox_q(s, e, dx, dy, dz);
-              const float ex = __builtin_amdgcn_exp2f(q);
-              const float he = (q >= a.thr) ? Hrow[x] * ex : 0.f;
-              m[0] += he;
-              m[1] = fmaf(he, dx, m[1]);
-              m[2] = fmaf(he, dy, m[2]);
-              m[3] = fmaf(he, dz, m[3]);
-              const float hx = he * dx, hy = he * dy;
-              m[4] = fmaf(hx, dx, m[4]);
-              m[5] = fmaf(hx, dy, m[5]);
-              m[6] = fmaf(hx, dz, m[6]);
-              m[7] = fmaf(hy, dy, m[7]);
-              m[8] = fmaf(hy, dz, m[8]);
-              m[9] = fmaf(he * dz, dz, m[9]);
+          for (int x = 0; x < kVSub; ++x) C0[x] = Cy[x] = Cz[x] = Cyy[x] = Cyz[x] = Czz[x] = 0.f;
+          if (chain) {
+            float e_z = __builtin_amdgcn_exp2f(dx0 * (c00 * dx0 + c01 * dy0 + c02 * dz0) +
+                                               dy0 * (c11 * dy0 + c12 * dz0) + c22 * dz0 * dz0);
+            float rx_z = __builtin_amdgcn_exp2f(c00 * (2.f * dx0 + 1.f) + c01 * dy0 + c02 * dz0);
+            float hy_z = __builtin_amdgcn_exp2f(c11 * (2.f * dy0 + 1.f) + c01 * dx0 + c12 * dz0);
+            float hz = __builtin_amdgcn_exp2f(c22 * (2.f * dz0 + 1.f) + c02 * dx0 + c12 * dy0);
+            const float rxx = __builtin_amdgcn_exp2f(2.f * c00), ryy = __builtin_amdgcn_exp2f(2.f * c11),
+                        rzz = __builtin_amdgcn_exp2f(2.f * c22), rxy = __builtin_amdgcn_exp2f(c01),
+                        rxz = __builtin_amdgcn_exp2f(c02), ryz = __builtin_amdgcn_exp2f(c12);
+            for (int z = 0; z < kVSub; ++z) {
+              const float dz = dz0 + (float)z, dzz = dz * dz;
+              float e_y = e_z, rx_y = rx_z, hy = hy_z;
+#pragma unroll
+              for (int y = 0; y < kVSub; ++y) {
+                const float dy = dy0 + (float)y, dyy = dy * dy, dyz = dy * dz;
+                const float4 Hr = *reinterpret_cast<const float4 *>(
+                    s_H + ((lz0 + z) * kVTile + (ly0 + y)) * kVTile + lx0);
+                const float Hx[kVSub] = {Hr.x, Hr.y, Hr.z, Hr.w};
+                float ev = e_y, rx = rx_y;
+#pragma unroll
+                for (int x = 0; x < kVSub; ++x) {
+                  const float he = (ev >= ethr) ? ev * Hx[x] : 0.f;
+                  C0[x] += he;
+                  Cy[x] = fmaf(he, dy, Cy[x]);
+                  Cz[x] = fmaf(he, dz, Cz[x]);
+                  Cyy[x] = fmaf(he, dyy, Cyy[x]);
+                  Cyz[x] = fmaf(he, dyz, Cyz[x]);
+                  Czz[x] = fmaf(he, dzz, Czz[x]);
+                  ev *= rx;
+                  rx *= rxx;
+                }
+                e_y *= hy;
+                hy *= ryy;
+                rx_y *= rxy;
+              }
+              e_z *= hz;
+              hz *= rzz;
+              hy_z *= ryz;
+              rx_z *= rxz;
+            }
+          } else {
+            for (int z = 0; z < kVSub; ++z) {
+              const float dz = oz + (float)z - cz, dzz = dz * dz;
+              for (int y = 0; y < kVSub; ++y) {
+                const float dy = oy + (float)y - cy, dyy = dy * dy, dyz = dy * dz;
+                const float *Hrow = s_H + ((lz0 + z) * kVTile + (ly0 + y)) * kVTile + lx0;
+#pragma unroll
+                for (int x = 0; x < kVSub; ++x) {
+                  const float dx = ox + (float)x - cx;
+                  const float q = dx * (c00 * dx + c01 * dy + c02 * dz) + dy * (c11 * dy + c12 * dz) +
+                                  c22 * dz * dz;
+                  const float ex = __builtin_amdgcn_exp2f(q);
+                  const float he = (q >= a.thr) ? Hrow[x] * ex : 0.f;
+                  C0[x] += he;
+                  Cy[x] = fmaf(he, dy, Cy[x]);
+                  Cz[x] = fmaf(he, dz, Cz[x]);
+                  Cyy[x] = fmaf(he, dyy, Cyy[x]);
+                  Cyz[x] = fmaf(he, dyz, Cyz[x]);
+                  Czz[x] = fmaf(he, dzz, Czz[x]);
+                }
+              }
             }
           }
+          float m[10];
+#pragma unroll
+          for (int k = 0; k < 10; ++k) m[k] = 0.f;
+#pragma unroll
+          for (int x = 0; x < kVSub; ++x) {
+            const float dx = dx0 + (float)x;
+            m[0] += C0[x];
+            const float t = C0[x] * dx;
+            m[1] += t;
+            m[4] = fmaf(t, dx, m[4]);
+            m[2] += Cy[x];
+            m[5] = fmaf(Cy[x], dx, m[5]);
+            m[3] += Cz[x];
+            m[6] = fmaf(Cz[x], dx, m[6]);
+            m[7] += Cyy[x];
+            m[8] += Cyz[x];
+            m[9] += Czz[x];
+          }
+          if (active)
+            for (int k = 0; k < 10; ++k) s_acc[w][k][e] += m[k];
         }
-        if (active)
-          for (int k = 0; k < 10; ++k) s_acc[w][k][e] += m[k];
       }
     }
     __syncthreads();

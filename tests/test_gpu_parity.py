@@ -194,6 +194,27 @@ def test_voxel_gradients(ops):
     assert el <= 1.0 and nr <= 1.0
 
 
+def test_voxel_gradients_thin_and_wide(ops):
+    """Widths from a tenth of a voxel to two voxels: the backward walks of the
+    wide Gaussians step exp2 by multiplication, those whose form leaves the
+    multiplicative range over a 4^3 sub-cube evaluate exp2 per voxel."""
+    g = scenes.random_scene(44, 260, lo=0.004, hi=0.06, box=0.45)
+    grid = Grid(37, 29, 33, (-0.5, -0.48, -0.52), (1 / 36, 1 / 28, 1 / 32))
+    smin = np.asarray(g.scale, np.float64).min(axis=1) / (1 / 28)
+    assert (smin < 0.3).mean() > 0.1 and (smin > 0.6).mean() > 0.3
+    H = upstream(7, (grid.nz, grid.ny, grid.nx))
+    t = _dev(g)
+    plan = ops.Plan()
+    ops.voxelize_forward(*t, ops.grid_from(grid), 3.0, plan)
+    grads = ops.voxelize_backward(*t, ops.grid_from(grid), torch.from_numpy(H).cuda(), plan, 3.0)
+    torch.cuda.synchronize()
+    ref = oracle.voxelize_grad(g, grid, H, 3.0, with_scale=True)
+    el, nr, det = parity.grad_violation(_np(grads), ref)
+    print(det)
+    _report("voxel grads thin and wide", max(el, nr))
+    assert el <= 1.0 and nr <= 1.0
+
+
 def test_backward_without_forward_and_accumulate(ops):
     """Backward on a fresh plan recomputes the binning; accumulate adds."""
     g = scenes.random_scene(44, 150)
