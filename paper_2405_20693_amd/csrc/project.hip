@@ -328,17 +328,20 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
   const Rec2 *rv = rec + (int64_t)v * a.M;
   const float thr = a.thr;
   float acc0 = 0.f, acc1 = 0.f;
+  // the next batch's entries are loaded while this batch renders
+  uint32_t ex_next = beg + tid < end ? list[beg + tid].x : 0u;
   for (uint32_t base = beg; base < end; base += kBlock) {
     const int n = (int)min((uint32_t)kBlock, end - base);
     __syncthreads();
     if (tid < n) {
-      const uint32_t ex = list[base + tid].x;
+      const uint32_t ex = ex_next;
       const float4 *p = reinterpret_cast<const float4 *>(rv + (ex & kEntryIndexMask));
       const float4 r0 = p[0], r1 = p[1];
       s_r0[tid] = r0;
       s_r1[tid] = make_float4(r1.x, r1.y, __log2f(fabsf(r1.y)), 0.f);
       s_m[tid] = (uint8_t)(ex >> kEntryMaskShift);
     }
+    ex_next = base + kBlock + tid < end ? list[base + kBlock + tid].x : 0u;
     __syncthreads();
     for (int c0 = 0; c0 < n; c0 += 64) {
       const int i = c0 + lane;
@@ -478,19 +481,34 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *_
             end);
   const Rec2 *rv = rec + (int64_t)v * a.M;
   const float ethr = __builtin_amdgcn_exp2f(a.thr);  // the cutoff on e = exp2(q)
+  // Software pipeline over the batches: entries are loaded two batches
+  // ahead and records one batch ahead, so staging does not wait on memory.
+  uint2 ent_cur = make_uint2(0u, 0u), ent_next = ent_cur;
+  float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0;
+  if (beg + tid < end) {
+    ent_cur = list[beg + tid];
+    const float4 *p = reinterpret_cast<const float4 *>(rv + (ent_cur.x & kEntryIndexMask));
+    q0 = p[0];
+    q1 = p[1];
+  }
+  if (beg + kBlock + tid < end) ent_next = list[beg + kBlock + tid];
   for (uint32_t base = beg; base < end; base += kBlock) {
     const int n = (int)min((uint32_t)kBlock, end - base);
     __syncthreads();
     uint32_t my_slot = 0;
     if (tid < n) {
-      const uint2 ent = list[base + tid];
-      my_slot = ent.y;
-      const float4 *p = reinterpret_cast<const float4 *>(rv + (ent.x & kEntryIndexMask));
-      float4 q0 = p[0], q1 = p[1];
+      my_slot = ent_cur.y;
       s_pu[tid] = q0.x; s_pv[tid] = q0.y; s_c00[tid] = q0.z; s_c01[tid] = q0.w;
       s_c11[tid] = q1.x;
-      s_m[tid] = (uint8_t)(ent.x >> kEntryMaskShift);
+      s_m[tid] = (uint8_t)(ent_cur.x >> kEntryMaskShift);
     }
+    if (base + kBlock + tid < end) {
+      const float4 *p = reinterpret_cast<const float4 *>(rv + (ent_next.x & kEntryIndexMask));
+      q0 = p[0];
+      q1 = p[1];
+    }
+    ent_cur = ent_next;
+    ent_next = (base + 2 * kBlock + tid < end) ? list[base + 2 * kBlock + tid] : make_uint2(0u, 0u);
 #pragma unroll
     for (int k = 0; k < 6; ++k)
 #pragma unroll
