@@ -292,15 +292,18 @@ void launch_proj_scatter(const ProjArgs &a, const Rec2 *rec, const uint32_t *his
 // ------------------------------------------------------- render forward --
 
 // One workgroup per (view, 16x16 tile); wave w owns the 8x8 sub-tile
-// (w & 1, w >> 1), one pixel per lane.  The tile's records are staged in LDS
-// in batches of 256.  For each chunk of 64 records, lane i takes record i if
-// its entry's mask marks the wave's sub-tile (set by the scatter) and
-// rewrites it relative to the sub-tile centre as
-//   q' + log2|rho_hat| = K0 + K1 x + K2 y + c00 x^2 + c01 x y + c11 y^2
-// (x, y: lane offsets from the centre), so that each kept record costs five
-// FMAs, one exp2 and a select per pixel.  The pixel sums sign(rho_hat)
-// exp2(...) over the kept records (a plain sum: Eq. 7 composes 2D Gaussians
-// additively, so the order is free).
+// (w & 1, w >> 1).  The tile's records are staged in LDS in batches of 256.
+// For each chunk of 64 records, lane i takes record i if its entry's mask
+// marks the wave's sub-tile (set by the scatter) and rewrites it relative to
+// the sub-tile centre as
+//   q' + log2|rho_hat| = K0 + K1 x + K2 y + c00 x^2 + c01 x y + c11 y^2.
+// The kept records are compacted and dealt to the wave's four 16-lane
+// quarters in turn; a lane evaluates a column of four pixels, the first with
+// five FMAs and the next three by forward differences down the column, so one
+// coefficient load from LDS serves four pixels.  The pixel sums
+// sign(rho_hat) exp2(...) over the kept records (a plain sum: Eq. 7 composes
+// 2D Gaussians additively, so the order is free); the four quarters' partial
+// sums are added in a fixed order at the end.
 __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *__restrict__ rec,
                                                        const uint2 *__restrict__ list,
                                                        const uint32_t *__restrict__ tile_start,
@@ -320,14 +323,17 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
   const int sx0 = tx * kTile + (w & 1) * kSub, sy0 = ty * kTile + (w >> 1) * kSub;
   const int px = sx0 + (lane & 7), py = sy0 + (lane >> 3);
   const float cxs = (float)sx0 + 0.5f * (kSub - 1), cys = (float)sy0 + 0.5f * (kSub - 1);
-  const float lx = (float)(lane & 7) - 0.5f * (kSub - 1), ly = (float)(lane >> 3) - 0.5f * (kSub - 1);
-  const float lxx = lx * lx, lxy = lx * ly, lyy = ly * ly;
+  // the lane's column of four pixels: x = j & 7, y = 4 (j >> 3) .. + 3 of its
+  // quarter's copy of the sub-tile (offsets from the sub-tile centre)
+  const int qd = lane >> 4, j = lane & 15, ry = (j >> 3) * 4;
+  const float lx = (float)(j & 7) - 0.5f * (kSub - 1), ly = (float)ry - 0.5f * (kSub - 1);
+  const float lxx = lx * lx, lxy = lx * ly, lyy = ly * ly, ly21 = 2.f * ly + 1.f;
   uint32_t beg, end;
   list_part(min(tile_start[item], a.cap), min(tile_start[item + 1], a.cap), part, a.parts, beg,
             end);
   const Rec2 *rv = rec + (int64_t)v * a.M;
   const float thr = a.thr;
-  float acc0 = 0.f, acc1 = 0.f;
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
   // the next batch's entries are loaded while this batch renders
   uint32_t ex_next = beg + tid < end ? list[beg + tid].x : 0u;
   for (uint32_t base = beg; base < end; base += kBlock) {
@@ -361,8 +367,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
           k1 = make_float4(c01, c11, thr + lr, rho > 0.f ? 1.f : -1.f);
         }
       }
-      // compact the kept records to consecutive slots; an odd count is padded
-      // with a record whose threshold no q reaches (it adds exactly 0)
+      // compact the kept records to consecutive slots
       const uint64_t mask = __ballot(hit);
       const int nk = __popcll(mask);
       if (hit) {
@@ -370,42 +375,42 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
         s_k[w][pos][0] = k0;
         s_k[w][pos][1] = k1;
       }
-      if ((nk & 1) && lane == 0) {
-        s_k[w][nk][0] = make_float4(0.f, 0.f, 0.f, 0.f);
-        s_k[w][nk][1] = make_float4(0.f, 0.f, INFINITY, 0.f);
-      }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const float4 *kp = &s_k[w][0][0];
-      for (int k = 0; k < nk; k += 2, kp += 4) {
-        const float4 a0 = kp[0], a1 = kp[1], b0 = kp[2], b1 = kp[3];
-        {
-          float q = fmaf(a0.y, lx, a0.x);
-          q = fmaf(a0.z, ly, q);
-          q = fmaf(a0.w, lxx, q);
-          q = fmaf(a1.x, lxy, q);
-          q = fmaf(a1.y, lyy, q);
+      for (int k = qd; k < nk; k += 4) {
+        const float4 a0 = s_k[w][k][0], a1 = s_k[w][k][1];
+        float q = fmaf(a0.y, lx, a0.x);
+        q = fmaf(a0.z, ly, q);
+        q = fmaf(a0.w, lxx, q);
+        q = fmaf(a1.x, lxy, q);
+        q = fmaf(a1.y, lyy, q);
+        float d = fmaf(a1.x, lx, a0.z);  // q(y + 1) - q(y) = K2 + c01 x + c11 (2 y + 1)
+        d = fmaf(a1.y, ly21, d);
+        const float dd = a1.y + a1.y;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
           const float e = (q >= a1.z) ? __builtin_amdgcn_exp2f(q) : 0.f;
-          acc0 = fmaf(a1.w, e, acc0);
-        }
-        {
-          float q = fmaf(b0.y, lx, b0.x);
-          q = fmaf(b0.z, ly, q);
-          q = fmaf(b0.w, lxx, q);
-          q = fmaf(b1.x, lxy, q);
-          q = fmaf(b1.y, lyy, q);
-          const float e = (q >= b1.z) ? __builtin_amdgcn_exp2f(q) : 0.f;
-          acc1 = fmaf(b1.w, e, acc1);
+          acc[r] = fmaf(a1.w, e, acc[r]);
+          q += d;
+          d += dd;
         }
       }
       __builtin_amdgcn_wave_barrier();  // the next chunk overwrites this wave's coefficients
     }
   }
+  // the four quarters' sums of each pixel, added in quarter order
+  float *red = reinterpret_cast<float *>(&s_k[w][0][0]);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) red[qd * 64 + (ry + r) * kSub + (j & 7)] = acc[r];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const float total = ((red[lane] + red[64 + lane]) + red[128 + lane]) + red[192 + lane];
   if (a.parts > 1)
-    partial[((int64_t)part * a.V * a.T + item) * kBlock + tid] = acc0 + acc1;
+    partial[((int64_t)part * a.V * a.T + item) * kBlock + tid] = total;
   else if (px < a.width && py < a.height)
-    image[((int64_t)v * a.height + py) * a.width + px] = acc0 + acc1;
+    image[((int64_t)v * a.height + py) * a.width + px] = total;
 }
 
 // Sum of the parts of each tile's pixels, in part order.
