@@ -381,7 +381,7 @@ gs_status proj_bin(gs_plan *pl, const gs_gaussians *g, const gs_view *views, int
   GS_TRY(ensure(pl, pl->p_tile_start, 4 * (VT + 1), s));
   GS_TRY(ensure(pl, pl->p_chunk_cnt, 4 * VC, s));
   GS_TRY(ensure(pl, pl->p_chunk_start, 4 * (VC + 1), s));
-  GS_TRY(ensure(pl, pl->p_offsets, 4 * VM, s));
+  GS_TRY(ensure(pl, pl->p_offsets, 4 * (VM + 1), s));  // + the slot total
   GS_TRY(ensure(pl, pl->p_totals, 16, s));
   GS_TRY(ensure_skipped(pl, s));
   StageTimer t_bin(pl, GS_STAGE_PROJ_BIN, s);
@@ -653,7 +653,7 @@ gs_status gs_plan_reserve(gs_plan *p, const gs_reserve *r, hipStream_t s) {
     GS_TRY(ensure(p, p->p_tile_start, 4 * (VT + 1), s));
     GS_TRY(ensure(p, p->p_chunk_cnt, 4 * VC, s));
     GS_TRY(ensure(p, p->p_chunk_start, 4 * (VC + 1), s));
-    GS_TRY(ensure(p, p->p_offsets, 4 * V * M, s));
+    GS_TRY(ensure(p, p->p_offsets, 4 * (V * M + 1), s));
     GS_TRY(ensure(p, p->p_totals, 16, s));
     GS_TRY(ensure(p, p->p_scan_tmp, 4 * (size_t)(2 * ((VT + 4095) / 4096) + 2 * ((VC + 4095) / 4096) + 2), s));
     GS_TRY(ensure(p, p->p_list, 8 * (size_t)std::max<int64_t>(E, 1), s));
@@ -871,7 +871,7 @@ static gs_status project_bwd(const gs_gaussians *g, const gs_view *views, int32_
   }
   {
     StageTimer t(plan, GS_STAGE_PROJ_CHAIN, stream);
-    launch_proj_chain(a, P<Rec2>(plan->p_rec), P<uint32_t>(plan->p_offsets),
+    launch_proj_chain(a, P<uint32_t>(plan->p_offsets),
                       P<float>(plan->p_slots), P<float>(plan->p_part), grads->mean, grads->scale,
                       grads->quat, grads->density, accumulate, st, stream);
   }

@@ -329,7 +329,7 @@ struct ChainStats {
   int32_t *visible;
   float scale;
 };
-void launch_proj_chain(const ProjArgs &a, const Rec2 *rec, const uint32_t *offsets,
+void launch_proj_chain(const ProjArgs &a, const uint32_t *offsets,
                        const float *slots, float *part, float *g_mean, float *g_scale,
                        float *g_quat, float *g_dens, int accumulate, const ChainStats &st,
                        hipStream_t s);

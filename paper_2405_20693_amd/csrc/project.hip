@@ -278,6 +278,9 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
     base += total;
     __syncthreads();  // the next batch restages
   }
+  // the slot total closes the offsets array (offsets[V M]); the last chunk of
+  // the last view ends there
+  if (v == a.V - 1 && c == a.C - 1 && tid == 0) offsets[(int64_t)a.V * a.M] = base;
 }
 
 void launch_proj_scatter(const ProjArgs &a, const Rec2 *rec, const uint32_t *hist,
@@ -683,12 +686,13 @@ constexpr int kChainParts = 16;  // gradient parts; +2 with statistics (NDC norm
 
 // A wave's 64 consecutive Gaussians own one contiguous run of slots per view
 // (offsets follow Gaussian order), so the wave stages that run in LDS with
-// 16-byte loads and each lane then sums its own slots from LDS; runs longer
-// than the staging buffer are read directly.  The slot buffer carries 16
-// bytes of padding for the rounded-up last load.
-constexpr int kChainStage = 512;  // float4 per wave (8 KB)
+// 16-byte loads, in rounds of up to 8 KB, and each lane sums its own slots
+// from LDS.  The slot buffer carries 16 bytes of padding for the rounded-up
+// last load.
+constexpr int kChainStage = 512;         // float4 per wave (8 KB)
+constexpr uint32_t kChainRound = 340u;   // slots per staging round
 
-__global__ __launch_bounds__(kBlock) void k_proj_chain(ProjArgs a, const Rec2 *__restrict__ rec,
+__global__ __launch_bounds__(kBlock) void k_proj_chain(ProjArgs a,
                                                        const uint32_t *__restrict__ offsets,
                                                        const float *__restrict__ slots,
                                                        float *__restrict__ part, int stats) {
@@ -707,25 +711,24 @@ __global__ __launch_bounds__(kBlock) void k_proj_chain(ProjArgs a, const Rec2 *_
   const int v0 = vc * kChainViews, v1 = min(v0 + kChainViews, a.V);
   const float4 *slots4 = reinterpret_cast<const float4 *>(slots);
   {
-    // the next view's tile rectangle and slot offset are loaded one view ahead
-    uint2 rw_next = make_uint2(1u, 0u);
-    uint32_t off_next = 0;
+    // The slots of (view, Gaussian) vg are [offsets[vg], offsets[vg + 1]):
+    // slots are numbered in (view, Gaussian) order and the array ends with the
+    // total.  The next view's pair of offsets is loaded one view ahead.
+    uint2 off_next = make_uint2(0u, 0u);
     if (G.ok && v0 < v1) {
       const int64_t vg = (int64_t)v0 * a.M + g;
-      rw_next = make_uint2(rec[vg].r0, rec[vg].r1);
-      off_next = offsets[vg];
+      off_next = make_uint2(offsets[vg], offsets[vg + 1]);
     }
     for (int v = v0; v < v1; ++v) {
       int cnt = 0;
       uint32_t off = 0;
       if (G.ok) {
-        cnt = rect_count(unpack_rect(rw_next.x, rw_next.y));
-        off = off_next;
+        off = off_next.x;
+        cnt = (int)(off_next.y - off_next.x);
         if ((uint64_t)off + (uint64_t)cnt > a.cap) cnt = 0;  // (beyond capacity: dropped)
         if (v + 1 < v1) {
           const int64_t vg = (int64_t)(v + 1) * a.M + g;
-          rw_next = make_uint2(rec[vg].r0, rec[vg].r1);
-          off_next = offsets[vg];
+          off_next = make_uint2(offsets[vg], offsets[vg + 1]);
         }
       }
       const uint64_t have = __ballot(cnt > 0);
@@ -733,9 +736,12 @@ __global__ __launch_bounds__(kBlock) void k_proj_chain(ProjArgs a, const Rec2 *_
       const int fl = __builtin_ctzll(have), ll = 63 - __builtin_clzll(have);
       const uint32_t lo = (uint32_t)__shfl((int)off, fl);
       const uint32_t hi = (uint32_t)__shfl((int)(off + (uint32_t)cnt), ll);
-      const uint64_t b4 = ((uint64_t)lo * 6u) >> 2, e4 = ((uint64_t)hi * 6u + 3u) >> 2;
-      const bool staged = e4 - b4 <= (uint64_t)kChainStage;
-      if (staged) {
+      // the run in rounds of kChainRound slots (at most 511 float4 with the
+      // alignment slack); each lane sums, in slot order, its slots in the round
+      float S[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      for (uint64_t clo = lo; clo < hi; clo += kChainRound) {  // 64-bit: no wrap near 2^32
+        const uint64_t chi = min((uint64_t)hi, clo + kChainRound);
+        const uint64_t b4 = (clo * 6u) >> 2, e4 = (chi * 6u + 3u) >> 2;
         const int n4 = (int)(e4 - b4);
 #pragma unroll
         for (int it = 0; it < kChainStage / 64; ++it) {
@@ -745,20 +751,15 @@ __global__ __launch_bounds__(kBlock) void k_proj_chain(ProjArgs a, const Rec2 *_
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      }
-      float S[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      if (cnt && staged) {
-        const float *sl = reinterpret_cast<const float *>(s_st[w]) + ((uint64_t)off * 6u - b4 * 4u);
-        for (int k = 0; k < cnt; ++k)
+        const uint64_t k0 = max((uint64_t)off, clo), k1 = min((uint64_t)off + (uint64_t)cnt, chi);
+        if (cnt && k0 < k1) {
+          const float *sl = reinterpret_cast<const float *>(s_st[w]) + (k0 * 6u - b4 * 4u);
+          for (int k = 0; k < (int)(k1 - k0); ++k)
 #pragma unroll
-          for (int j = 0; j < 6; ++j) S[j] += sl[6 * k + j];
-      } else if (cnt) {
-        const float *sl = slots + (int64_t)off * 6;
-        for (int k = 0; k < cnt; ++k)
-#pragma unroll
-          for (int j = 0; j < 6; ++j) S[j] += sl[6 * k + j];
+            for (int j = 0; j < 6; ++j) S[j] += sl[6 * k + j];
+        }
+        __builtin_amdgcn_wave_barrier();  // the next round restages
       }
-      __builtin_amdgcn_wave_barrier();  // the next view restages
       if (!cnt) continue;
       const DevView V = a.views[v];
       Proj2 P;
@@ -899,15 +900,14 @@ __global__ __launch_bounds__(kBlock) void k_proj_chain_reduce(ProjArgs a, int n_
 
 int proj_chain_chunks(int n_views) { return (n_views + kChainViews - 1) / kChainViews; }
 
-void launch_proj_chain(const ProjArgs &a, const Rec2 *rec, const uint32_t *offsets,
+void launch_proj_chain(const ProjArgs &a, const uint32_t *offsets,
                        const float *slots, float *part, float *g_mean, float *g_scale,
                        float *g_quat, float *g_dens, int accumulate, const ChainStats &st,
                        hipStream_t s) {
   unsigned nb = (unsigned)((a.M + kBlock - 1) / kBlock);
   const int nc = proj_chain_chunks(a.V);
   const int stats = st.ndc_sum != nullptr;
-  hipLaunchKernelGGL(k_proj_chain, dim3(nb, nc), dim3(kBlock), 0, s, a, rec, offsets, slots, part,
-                     stats);
+  hipLaunchKernelGGL(k_proj_chain, dim3(nb, nc), dim3(kBlock), 0, s, a, offsets, slots, part, stats);
   hipLaunchKernelGGL(k_proj_chain_reduce, dim3(nb), dim3(kBlock), 0, s, a, nc, part, g_mean,
                      g_scale, g_quat, g_dens, accumulate, st);
 }
