@@ -229,31 +229,45 @@ __device__ inline float vox_q(const float (*s)[kBlock], int e, float dx, float d
          s[8][e] * dz * dz;
 }
 
-// One workgroup per 8^3 tile; wave w owns the 4^3 sub-cubes w and w + 4,
-// one voxel per lane; ballot-culled records from an LDS batch.
+// One workgroup per 8^3 tile; wave w owns the 4^3 sub-cubes w and w + 4.
+// For each chunk of 64 staged records, lane i tests record i against the
+// sub-cube (box overlap and the concave-bound cull) and, if it may reach it,
+// rewrites it relative to the sub-cube centre: with l the voxel offset from
+// the centre,
+//   q'(l) = K0 + K1 lx + K2 ly + c00 lx^2 + c01 lx ly + c11 ly^2   (lz = -3/2)
+// and down z by the differences D0 + c02 lx + c12 ly, stepping by 2 c22.  The
+// kept records are compacted and dealt to the wave's four 16-lane quarters;
+// a lane evaluates a column of four voxels along z, so one coefficient load
+// from LDS serves four voxels.  The quarters' partial sums are added in a
+// fixed order at the end.
 __global__ __launch_bounds__(kBlock) void k_vox_fwd(VoxArgs a, const Rec3 *__restrict__ rec,
                                                     const uint32_t *__restrict__ list,
                                                     const uint32_t *__restrict__ tile_start,
                                                     float *__restrict__ vol,
                                                     float *__restrict__ partial) {
   __shared__ float s[13][kBlock];
+  __shared__ float4 s_k[4][64][3];  // per wave: compacted coefficients of the kept records
   const int wi = xcd_remap(blockIdx.x, gridDim.x);
   const int item = wi / a.parts, part = wi - item * a.parts;
   const VoxTile T = decode_item(a, item);
   if (!T.valid) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  float acc[2] = {0.f, 0.f};
-  int vx[2], vy[2], vz[2];
+  // the lane's column of four voxels in its quarter's copy of a sub-cube
+  const int qd = lane >> 4, j = lane & 15;
+  const float hs = 0.5f * (kVSub - 1);
+  const float lx = (float)(j & 3) - hs, ly = (float)(j >> 2) - hs;
+  const float lxx = lx * lx, lxy = lx * ly, lyy = ly * ly;
+  float acc[2][kVSub];
   float ox[2], oy[2], oz[2];
   for (int k = 0; k < 2; ++k) {
     const int sc = w + 4 * k;
     ox[k] = (float)(T.tx * kVTile + (sc & 1) * kVSub);
     oy[k] = (float)(T.ty * kVTile + ((sc >> 1) & 1) * kVSub);
     oz[k] = (float)(T.tz * kVTile + (sc >> 2) * kVSub);
-    vx[k] = (int)ox[k] + (lane & 3);
-    vy[k] = (int)oy[k] + ((lane >> 2) & 3);
-    vz[k] = (int)oz[k] + (lane >> 4);
+#pragma unroll
+    for (int z = 0; z < kVSub; ++z) acc[k][z] = 0.f;
   }
+  const float thr = a.thr;
   uint32_t beg, end;
   list_part(min(tile_start[item], a.cap), min(tile_start[item + 1], a.cap), part, a.parts, beg,
             end);
@@ -267,28 +281,80 @@ __global__ __launch_bounds__(kBlock) void k_vox_fwd(VoxArgs a, const Rec3 *__res
       for (int c0 = 0; c0 < n; c0 += 64) {
         const int i = c0 + lane;
         const bool hit = (i < n) && box_hits(s, i, ox[k], oy[k], oz[k]) &&
-                         box_may_reach(s, i, ox[k], oy[k], oz[k], a.thr);
-        uint64_t mask = __ballot(hit);
-        while (mask) {
-          const int e = c0 + __builtin_ctzll(mask);
-          mask &= mask - 1;
-          const float q = vox_q(s, e, (float)vx[k] - s[0][e], (float)vy[k] - s[1][e],
-                                (float)vz[k] - s[2][e]);
-          const float ex = __builtin_amdgcn_exp2f(q);
-          acc[k] += (q >= a.thr) ? s[9][e] * ex : 0.f;
+                         box_may_reach(s, i, ox[k], oy[k], oz[k], thr);
+        float4 k0, k1, k2;
+        if (hit) {
+          const float c00 = s[3][i], c01 = s[4][i], c02 = s[5][i], c11 = s[6][i], c12 = s[7][i],
+                      c22 = s[8][i];
+          // record centre relative to the sub-cube centre
+          const float u = s[0][i] - (ox[k] + hs), v = s[1][i] - (oy[k] + hs),
+                      ww = s[2][i] - (oz[k] + hs);
+          const float K0 = u * (c00 * u + c01 * v + c02 * ww) + v * (c11 * v + c12 * ww) + c22 * ww * ww;
+          const float K1 = -(2.f * c00 * u + c01 * v + c02 * ww);
+          const float K2 = -(c01 * u + 2.f * c11 * v + c12 * ww);
+          const float K3 = -(c02 * u + c12 * v + 2.f * c22 * ww);
+          // fold lz = -hs into the x-y form, and the first z difference
+          k0 = make_float4(K0 - hs * K3 + hs * hs * c22, K1 - hs * c02, K2 - hs * c12, c00);
+          k1 = make_float4(c01, c11, K3 + c22 * (1.f - 2.f * hs), c02);
+          k2 = make_float4(c12, 2.f * c22, s[9][i], 0.f);
         }
+        const uint64_t mask = __ballot(hit);
+        const int nk = __popcll(mask);
+        if (hit) {
+          const int pos = lanes_below(mask);
+          s_k[w][pos][0] = k0;
+          s_k[w][pos][1] = k1;
+          s_k[w][pos][2] = k2;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int r = qd; r < nk; r += 4) {
+          const float4 a0 = s_k[w][r][0], a1 = s_k[w][r][1], a2 = s_k[w][r][2];
+          float q = fmaf(a0.y, lx, a0.x);
+          q = fmaf(a0.z, ly, q);
+          q = fmaf(a0.w, lxx, q);
+          q = fmaf(a1.x, lxy, q);
+          q = fmaf(a1.y, lyy, q);
+          float d = fmaf(a1.w, lx, a1.z);  // q'(z + 1) - q'(z) at the first voxel
+          d = fmaf(a2.x, ly, d);
+#pragma unroll
+          for (int z = 0; z < kVSub; ++z) {
+            const float e = (q >= thr) ? __builtin_amdgcn_exp2f(q) : 0.f;
+            acc[k][z] = fmaf(a2.z, e, acc[k][z]);
+            q += d;
+            d += a2.y;
+          }
+        }
+        __builtin_amdgcn_wave_barrier();  // the next chunk overwrites this wave's coefficients
       }
     }
   }
+  // the four quarters' sums of each voxel (lane x + 4 y + 16 z), in quarter order
+  float total[2];
+  float *red = reinterpret_cast<float *>(&s_k[w][0][0]);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+#pragma unroll
+    for (int z = 0; z < kVSub; ++z) red[qd * 64 + z * 16 + j] = acc[k][z];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    total[k] = ((red[lane] + red[64 + lane]) + red[128 + lane]) + red[192 + lane];
+    __builtin_amdgcn_wave_barrier();
+  }
   if (a.parts > 1) {
     float *pp = partial + ((int64_t)part * a.G * a.Tg + item) * (2 * kBlock);
-    pp[tid] = acc[0];
-    pp[kBlock + tid] = acc[1];
+    pp[tid] = total[0];
+    pp[kBlock + tid] = total[1];
     return;
   }
-  for (int k = 0; k < 2; ++k)
-    if (vx[k] < a.nx && vy[k] < a.ny && vz[k] < a.nz)
-      vol[((int64_t)vz[k] * a.ny + vy[k]) * a.nx + vx[k]] = acc[k];
+  for (int k = 0; k < 2; ++k) {
+    const int vx = (int)ox[k] + (lane & 3), vy = (int)oy[k] + ((lane >> 2) & 3),
+              vz = (int)oz[k] + (lane >> 4);
+    if (vx < a.nx && vy < a.ny && vz < a.nz)
+      vol[((int64_t)vz * a.ny + vy) * a.nx + vx] = total[k];
+  }
 }
 
 // Sum of the parts of each tile's voxels, in part order (same voxel mapping
