@@ -147,19 +147,46 @@ void launch_proj_hist(const ProjArgs &a, Rec2 *rec, uint32_t *hist, uint32_t *ch
                      chunk_cnt, skipped);
 }
 
-// Per (group, tile): exclusive prefix over chunks, in place; tile totals.
-__global__ __launch_bounds__(kBlock) void k_hist_colscan(int groups, int C, int T,
-                                                         uint32_t *__restrict__ hist,
-                                                         uint32_t *__restrict__ tile_total) {
-  int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (id >= (int64_t)groups * T) return;
-  int grp = (int)(id / T), t = (int)(id - (int64_t)grp * T);
-  uint32_t run = 0;
+// Per (group, tile) column: exclusive prefix over the chunks, in place, and
+// the tile totals.  A workgroup takes 64 consecutive columns (lane = column,
+// so each load instruction reads 256 contiguous bytes) and splits every column
+// into kColSeg segments, one per wave: each wave sums its segment, the
+// segment sums are scanned through LDS, and each wave rescans its segment
+// from its base.  Few-view calls bin in hundreds of small chunks, where one
+// thread per column would walk the whole column serially.
+constexpr int kColSeg = 16;
+
+__global__ __launch_bounds__(64 * kColSeg) void k_hist_colscan(int groups, int C, int T,
+                                                               uint32_t *__restrict__ hist,
+                                                               uint32_t *__restrict__ tile_total) {
+  __shared__ uint32_t s_sum[kColSeg][64];
+  const int lane = threadIdx.x & 63, seg = threadIdx.x >> 6;
+  const int64_t col = (int64_t)blockIdx.x * 64 + lane;
+  const bool ok = col < (int64_t)groups * T;
+  const int grp = ok ? (int)(col / T) : 0, t = ok ? (int)(col - (int64_t)grp * T) : 0;
   uint32_t *h = hist + (int64_t)grp * C * T + t;
-  // batches of 8 independent loads, then the prefix (long chunk columns when
-  // one view is binned in many small chunks)
-  int c = 0;
-  for (; c + 8 <= C; c += 8) {
+  const int L = (C + kColSeg - 1) / kColSeg;
+  const int c0 = min(C, seg * L), c1 = min(C, c0 + L);
+  uint32_t sum = 0;
+  if (ok) {
+    int c = c0;
+    for (; c + 8 <= c1; c += 8) {  // batches of 8 independent loads
+      uint32_t x[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) x[k] = h[(int64_t)(c + k) * T];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) sum += x[k];
+    }
+    for (; c < c1; ++c) sum += h[(int64_t)c * T];
+  }
+  s_sum[seg][lane] = sum;
+  __syncthreads();
+  uint32_t run = 0;
+  for (int k = 0; k < seg; ++k) run += s_sum[k][lane];
+  if (!ok) return;
+  if (seg == kColSeg - 1) tile_total[col] = run + sum;
+  int c = c0;
+  for (; c + 8 <= c1; c += 8) {
     uint32_t x[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) x[k] = h[(int64_t)(c + k) * T];
@@ -169,19 +196,18 @@ __global__ __launch_bounds__(kBlock) void k_hist_colscan(int groups, int C, int 
       run += x[k];
     }
   }
-  for (; c < C; ++c) {
+  for (; c < c1; ++c) {
     const uint32_t x = h[(int64_t)c * T];
     h[(int64_t)c * T] = run;
     run += x;
   }
-  tile_total[id] = run;
 }
 
 void launch_hist_colscan(int groups, int C, int T, uint32_t *hist, uint32_t *tile_total,
                          hipStream_t s) {
-  int64_t n = (int64_t)groups * T;
-  hipLaunchKernelGGL(k_hist_colscan, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                     s, groups, C, T, hist, tile_total);
+  const int64_t n = (int64_t)groups * T;
+  hipLaunchKernelGGL(k_hist_colscan, dim3((unsigned)((n + 63) / 64)), dim3(64 * kColSeg), 0, s,
+                     groups, C, T, hist, tile_total);
 }
 
 // Grid (C, V).  Writes each Gaussian's tile entries at its tiles' cursors and
