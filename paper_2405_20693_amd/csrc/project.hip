@@ -324,15 +324,23 @@ void launch_proj_scatter(const ProjArgs &a, const Rec2 *rec, const uint32_t *his
 // (w & 1, w >> 1).  The tile's records are staged in LDS in batches of 256.
 // For each chunk of 64 records, lane i takes record i if its entry's mask
 // marks the wave's sub-tile (set by the scatter) and rewrites it relative to
-// the sub-tile centre as
-//   q' + log2|rho_hat| = K0 + K1 x + K2 y + c00 x^2 + c01 x y + c11 y^2.
-// The kept records are compacted and dealt to the wave's four 16-lane
-// quarters in turn; a lane evaluates a column of four pixels, the first with
-// five FMAs and the next three by forward differences down the column, so one
-// coefficient load from LDS serves four pixels.  The pixel sums
+// the sub-tile centre: with x, y the pixel offsets from the centre,
+//   q' + log2|rho_hat| = A0 + A1 x + c00 x^2          on the first row,
+// stepping down a column by D(y) = B0 + c01 x, D itself by 2 c11.  The kept
+// records are compacted and dealt to the wave's eight 8-lane groups in turn;
+// each lane evaluates one column of eight pixels.  Where every value of
+// e = exp2(q') over the sub-tile is a normal FP32 number (form at most
+// kFwdChainRange there, its maximum being at a corner, and |rho_hat| not
+// tiny), e is stepped down the column by multiplication, e *= exp2(D),
+// exp2(D) *= exp2(2 c11): two exp2 per column instead of eight; the sign of
+// rho_hat rides on e and the cutoff becomes |e| >= exp2(threshold).  Other
+// records keep exp2 per pixel with q' forward-differenced; the two kinds are
+// queued apart, so a record's path is its own.  The pixel sums
 // sign(rho_hat) exp2(...) over the kept records (a plain sum: Eq. 7 composes
-// 2D Gaussians additively, so the order is free); the four quarters' partial
-// sums are added in a fixed order at the end.
+// 2D Gaussians additively, so the order is free); the groups' partial sums
+// are added in a fixed order at the end.
+constexpr float kFwdChainRange = 100.f;
+
 __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *__restrict__ rec,
                                                        const uint2 *__restrict__ list,
                                                        const uint32_t *__restrict__ tile_start,
@@ -343,6 +351,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
   __shared__ float4 s_r0[kBlock], s_r1[kBlock];
   __shared__ uint8_t s_m[kBlock];
   // per wave: the kept records' coefficients, compacted, two float4 each
+  // (multiplicative records from the front, per-pixel exp2 records from the back)
   __shared__ float4 s_k[4][64][2];
   const int wi = xcd_remap(blockIdx.x, gridDim.x);
   const int item = wi / a.parts, part = wi - item * a.parts;
@@ -351,18 +360,19 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int sx0 = tx * kTile + (w & 1) * kSub, sy0 = ty * kTile + (w >> 1) * kSub;
   const int px = sx0 + (lane & 7), py = sy0 + (lane >> 3);
-  const float cxs = (float)sx0 + 0.5f * (kSub - 1), cys = (float)sy0 + 0.5f * (kSub - 1);
-  // the lane's column of four pixels: x = j & 7, y = 4 (j >> 3) .. + 3 of its
-  // quarter's copy of the sub-tile (offsets from the sub-tile centre)
-  const int qd = lane >> 4, j = lane & 15, ry = (j >> 3) * 4;
-  const float lx = (float)(j & 7) - 0.5f * (kSub - 1), ly = (float)ry - 0.5f * (kSub - 1);
-  const float lxx = lx * lx, lxy = lx * ly, lyy = ly * ly, ly21 = 2.f * ly + 1.f;
+  const float hs = 0.5f * (kSub - 1);
+  const float cxs = (float)sx0 + hs, cys = (float)sy0 + hs;
+  // the lane's column: x = lane & 7 of its group's copy of the sub-tile
+  const int grp = lane >> 3;
+  const float lx = (float)(lane & 7) - hs, lxx = lx * lx;
   uint32_t beg, end;
   list_part(min(tile_start[item], a.cap), min(tile_start[item + 1], a.cap), part, a.parts, beg,
             end);
   const Rec2 *rv = rec + (int64_t)v * a.M;
   const float thr = a.thr;
-  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  float acc[kSub];
+#pragma unroll
+  for (int y = 0; y < kSub; ++y) acc[y] = 0.f;
   // the next batch's entries are loaded while this batch renders
   uint32_t ex_next = beg + tid < end ? list[beg + tid].x : 0u;
   for (uint32_t base = beg; base < end; base += kBlock) {
@@ -380,7 +390,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
     __syncthreads();
     for (int c0 = 0; c0 < n; c0 += 64) {
       const int i = c0 + lane;
-      bool hit = false;
+      bool hit = false, chain = false;
       float4 k0, k1;
       if (i < n && ((s_m[i] >> w) & 1u)) {
         const float4 r0 = s_r0[i], r1 = s_r1[i];
@@ -392,50 +402,74 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
           const float K0 = u * (c00 * u + c01 * vv) + c11 * vv * vv + lr;
           const float K1 = -(2.f * c00 * u + c01 * vv);
           const float K2 = -(c01 * u + 2.f * c11 * vv);
-          k0 = make_float4(K0, K1, K2, c00);
-          k1 = make_float4(c01, c11, thr + lr, rho > 0.f ? 1.f : -1.f);
+          const float A0 = K0 - hs * K2 + hs * hs * c11, A1 = K1 - hs * c01;
+          const float B0 = K2 + c11 * (1.f - 2.f * hs);
+          // largest positive form -q over the sub-tile (at a corner)
+          float fmax = 0.f;
+#pragma unroll
+          for (int cx = 0; cx < 2; ++cx)
+#pragma unroll
+            for (int cy = 0; cy < 2; ++cy) {
+              const float dx = (cx ? hs : -hs) - u, dy = (cy ? hs : -hs) - vv;
+              fmax = fmaxf(fmax, -(dx * (c00 * dx + c01 * dy) + c11 * dy * dy));
+            }
+          chain = fmax + fmaxf(-lr, 0.f) <= kFwdChainRange;
+          k0 = make_float4(A0, A1, c00, B0);
+          k1 = chain ? make_float4(c01, __builtin_amdgcn_exp2f(2.f * c11),
+                                   copysignf(__builtin_amdgcn_exp2f(thr + lr), rho), 0.f)
+                     : make_float4(c01, 2.f * c11, thr + lr, rho > 0.f ? 1.f : -1.f);
         }
       }
-      // compact the kept records to consecutive slots
-      const uint64_t mask = __ballot(hit);
-      const int nk = __popcll(mask);
+      // compact: multiplicative records from the front, the others from the back
+      const uint64_t mc = __ballot(hit && chain), me = __ballot(hit && !chain);
+      const int nc = __popcll(mc), ne = __popcll(me);
       if (hit) {
-        const int pos = lanes_below(mask);
+        const int pos = chain ? lanes_below(mc) : 63 - lanes_below(me);
         s_k[w][pos][0] = k0;
         s_k[w][pos][1] = k1;
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      for (int k = qd; k < nk; k += 4) {
-        const float4 a0 = s_k[w][k][0], a1 = s_k[w][k][1];
-        float q = fmaf(a0.y, lx, a0.x);
-        q = fmaf(a0.z, ly, q);
-        q = fmaf(a0.w, lxx, q);
-        q = fmaf(a1.x, lxy, q);
-        q = fmaf(a1.y, lyy, q);
-        float d = fmaf(a1.x, lx, a0.z);  // q(y + 1) - q(y) = K2 + c01 x + c11 (2 y + 1)
-        d = fmaf(a1.y, ly21, d);
-        const float dd = a1.y + a1.y;
+      for (int r = grp; r < nc; r += 8) {
+        const float4 a0 = s_k[w][r][0], a1 = s_k[w][r][1];
+        const float q0 = fmaf(a0.z, lxx, fmaf(a0.y, lx, a0.x));
+        const float d0 = fmaf(a1.x, lx, a0.w);
+        float e = copysignf(__builtin_amdgcn_exp2f(q0), a1.z);
+        float rr = __builtin_amdgcn_exp2f(d0);
+        const float et = fabsf(a1.z), R = a1.y;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float e = (q >= a1.z) ? __builtin_amdgcn_exp2f(q) : 0.f;
-          acc[r] = fmaf(a1.w, e, acc[r]);
+        for (int y = 0; y < kSub; ++y) {
+          acc[y] += (fabsf(e) >= et) ? e : 0.f;
+          e *= rr;
+          rr *= R;
+        }
+      }
+      for (int r = grp; r < ne; r += 8) {
+        const float4 a0 = s_k[w][63 - r][0], a1 = s_k[w][63 - r][1];
+        float q = fmaf(a0.z, lxx, fmaf(a0.y, lx, a0.x));
+        float d = fmaf(a1.x, lx, a0.w);
+#pragma unroll
+        for (int y = 0; y < kSub; ++y) {
+          const float ev = (q >= a1.z) ? __builtin_amdgcn_exp2f(q) : 0.f;
+          acc[y] = fmaf(a1.w, ev, acc[y]);
           q += d;
-          d += dd;
+          d += a1.y;
         }
       }
       __builtin_amdgcn_wave_barrier();  // the next chunk overwrites this wave's coefficients
     }
   }
-  // the four quarters' sums of each pixel, added in quarter order
+  // the eight groups' sums of each pixel (lane x + 8 y), added in group order
   float *red = reinterpret_cast<float *>(&s_k[w][0][0]);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) red[qd * 64 + (ry + r) * kSub + (j & 7)] = acc[r];
+  for (int y = 0; y < kSub; ++y) red[grp * 64 + y * kSub + (lane & 7)] = acc[y];
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const float total = ((red[lane] + red[64 + lane]) + red[128 + lane]) + red[192 + lane];
+  float total = 0.f;
+#pragma unroll
+  for (int g = 0; g < 8; ++g) total += red[g * 64 + lane];
   if (a.parts > 1)
     partial[((int64_t)part * a.V * a.T + item) * kBlock + tid] = total;
   else if (px < a.width && py < a.height)

@@ -167,6 +167,25 @@ def test_cone_gradients_thin_and_wide(ops):
     assert el <= 1.0 and nr <= 1.0
 
 
+def test_signed_densities(ops):
+    """Densities of both signs (the projection is linear in them), thin and
+    wide Gaussians: the forward's multiplicative columns carry the sign on
+    exp2, its per-pixel path multiplies by it; image and gradients against
+    the oracle."""
+    g = scenes.random_scene(45, 300, lo=0.006, hi=0.1, box=0.5, rho=(-1.0, 1.0))
+    assert (g.density < 0).mean() > 0.3 and (g.density > 0).mean() > 0.3
+    th = [0.7, 2.6]
+    views = ops.Views.cone(th, 13.64, 20.46, 80, 72, 0.045)
+    ov = [oracle.cone_view(t, 13.64, 20.46, 80, 72, 0.045) for t in th]
+    img, _ = _proj_fwd(ops, g, views)
+    v, _ = parity.forward_violation(img, oracle.project(g, ov))
+    _report("signed densities forward", v)
+    assert v <= 1.0
+    el, nr = _check_proj_grad(ops, g, views, ov, 8)
+    _report("signed densities grads", max(el, nr))
+    assert el <= 1.0 and nr <= 1.0
+
+
 def test_parallel_gradients(ops):
     from scipy.spatial.transform import Rotation
     g = scenes.random_scene(42, 200, lo=0.03, hi=0.12, box=0.6)
