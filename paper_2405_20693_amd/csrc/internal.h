@@ -236,6 +236,23 @@ __device__ inline int lanes_below(uint64_t mask) {
                                         __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Sum of n strided values p[0], p[stride], ... added in index order, with
+// four loads in flight (a run-time trip count otherwise issues one at a time).
+__device__ inline float strided_sum(const float *__restrict__ p, int64_t stride, int n) {
+  float acc = 0.f;
+  int k = 0;
+  for (; k + 4 <= n; k += 4) {
+    const float x0 = p[k * stride], x1 = p[(k + 1) * stride], x2 = p[(k + 2) * stride],
+                x3 = p[(k + 3) * stride];
+    acc += x0;
+    acc += x1;
+    acc += x2;
+    acc += x3;
+  }
+  for (; k < n; ++k) acc += p[k * stride];
+  return acc;
+}
+
 // Tile-list entry (Gaussian index | sub-tile mask << kEntryMaskShift, backward
 // slot): bit w of the mask is set when the cutoff ellipse meets 8x8 sub-tile w
 // of the 16x16 tile (w = (x half) + 2 (y half)).

@@ -486,8 +486,7 @@ __global__ __launch_bounds__(kBlock) void k_render_parts(ProjArgs a, const float
   const int py = ty * kTile + (w >> 1) * kSub + (lane >> 3);
   const int64_t stride = (int64_t)a.V * a.T * kBlock;
   const float *p = partial + (int64_t)item * kBlock + tid;
-  float acc = 0.f;
-  for (int k = 0; k < a.parts; ++k) acc += p[k * stride];
+  const float acc = strided_sum(p, stride, a.parts);
   if (px < a.width && py < a.height) image[((int64_t)v * a.height + py) * a.width + px] = acc;
 }
 

@@ -372,8 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_vox_parts(VoxArgs a, const float *__
     const int vy = T.ty * kVTile + ((sc >> 1) & 1) * kVSub + ((lane >> 2) & 3);
     const int vz = T.tz * kVTile + (sc >> 2) * kVSub + (lane >> 4);
     const float *p = partial + (int64_t)item * (2 * kBlock) + k * kBlock + tid;
-    float acc = 0.f;
-    for (int j = 0; j < a.parts; ++j) acc += p[j * stride];
+    const float acc = strided_sum(p, stride, a.parts);
     if (vx < a.nx && vy < a.ny && vz < a.nz) vol[((int64_t)vz * a.ny + vy) * a.nx + vx] = acc;
   }
 }
