@@ -290,6 +290,8 @@ constexpr int kDW = kSW + 2 * kR;  // 42: coefficient region edge
 constexpr int kXW = kDW + 2 * kR;  // 52: input region edge
 constexpr int kF1 = 7;             // stage 1: outputs per row task and per column task
 constexpr int kF2 = 8;             // stage 2: outputs per row task
+constexpr int kR1 = 11, kRSeg = 4;  // stage 1 row pass: outputs per task, tasks per row
+static_assert(kR1 * kRSeg >= kDW && kR1 * (kRSeg - 1) < kDW, "row segments cover the row");
 
 __global__ __launch_bounds__(kBlock) void k_ssim_fused(const float *__restrict__ x,
                                                        const float *__restrict__ y, int n, int h,
@@ -323,20 +325,23 @@ __global__ __launch_bounds__(kBlock) void k_ssim_fused(const float *__restrict__
   float m[5][kF1];
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
-    for (int task = tid; task < kXW * (kDW / kF1); task += kBlock) {
-      const int r = task / (kDW / kF1), c0 = (task - r * (kDW / kF1)) * kF1;
-      float win[kF1 + kWin - 1];
+    // row pass: 52 rows x 4 segments of kR1 outputs (the last one 9), one
+    // task per thread
+    if (tid < kXW * kRSeg) {
+      const int r = tid / kRSeg, c0 = (tid - r * kRSeg) * kR1;
+      float win[kR1 + kWin - 1];
 #pragma unroll
-      for (int k = 0; k < kF1 + kWin - 1; ++k) {
-        const float xv = sx[r * kXW + c0 + k], yv = sy[r * kXW + c0 + k];
+      for (int k = 0; k < kR1 + kWin - 1; ++k) {
+        const bool in = c0 + k < kXW;  // the last segment's window ends at the row
+        const float xv = in ? sx[r * kXW + c0 + k] : 0.f, yv = in ? sy[r * kXW + c0 + k] : 0.f;
         win[k] = q == 0 ? xv : q == 1 ? yv : q == 2 ? xv * xv : q == 3 ? yv * yv : xv * yv;
       }
 #pragma unroll
-      for (int o = 0; o < kF1; ++o) {
+      for (int o = 0; o < kR1; ++o) {
         float acc = 0.f;
 #pragma unroll
         for (int k = 0; k < kWin; ++k) acc = fmaf(c_win[k], win[o + k], acc);
-        s_h[r * kDW + c0 + o] = acc;
+        if (c0 + o < kDW) s_h[r * kDW + c0 + o] = acc;
       }
     }
     __syncthreads();
