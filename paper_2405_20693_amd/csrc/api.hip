@@ -958,7 +958,7 @@ gs_status gs_voxelize_bwd(const gs_gaussians *g, const gs_grid *grid, float cuto
   }
   {
     StageTimer t(plan, GS_STAGE_VOX_CHAIN, stream);
-    launch_vox_chain(a, P<Rec3>(plan->v_rec), P<uint32_t>(plan->v_offsets),
+    launch_vox_chain(a, P<uint32_t>(plan->v_offsets),
                      P<float>(plan->v_slots), grads->mean, grads->scale, grads->quat,
                      grads->density, accumulate, stream);
   }

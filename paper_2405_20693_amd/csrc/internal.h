@@ -385,9 +385,9 @@ void launch_vox_fwd(const VoxArgs &a, const Rec3 *rec, const uint32_t *list,
 void launch_vox_bwd(const VoxArgs &a, const Rec3 *rec, const uint32_t *list,
                     const uint32_t *tile_start, const uint32_t *offsets, const float *grad_volume,
                     float *slots, hipStream_t s);
-void launch_vox_chain(const VoxArgs &a, const Rec3 *rec, const uint32_t *offsets,
-                      const float *slots, float *g_mean, float *g_scale, float *g_quat,
-                      float *g_dens, int accumulate, hipStream_t s);
+void launch_vox_chain(const VoxArgs &a, const uint32_t *offsets, const float *slots,
+                      float *g_mean, float *g_scale, float *g_quat, float *g_dens, int accumulate,
+                      hipStream_t s);
 
 void launch_ssim_coeffs(const float *x, const float *y, int n, int h, int w, float *coef,
                         float *partials, hipStream_t s);

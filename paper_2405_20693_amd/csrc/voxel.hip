@@ -600,21 +600,27 @@ void launch_vox_bwd(const VoxArgs &a, const Rec3 *rec, const uint32_t *list,
 
 // One thread per Gaussian: sum the tile slots' moments and apply the chain
 // rule through the index-unit conic, P = R S^-2 R^T and the quaternion.
-__global__ __launch_bounds__(kBlock) void k_vox_chain(VoxArgs a, const Rec3 *__restrict__ rec,
+// Slots are numbered in Gaussian order and the offsets array ends with the
+// total, so a Gaussian's slot count is the difference of its offsets; the
+// many Gaussians with none (outside the block) read neither their record nor
+// their parameters.
+__global__ __launch_bounds__(kBlock) void k_vox_chain(VoxArgs a,
                                                       const uint32_t *__restrict__ offsets,
                                                       const float *__restrict__ slots,
                                                       float *g_mean, float *g_scale, float *g_quat,
                                                       float *g_dens, int accumulate) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (g >= a.M) return;
-  Gauss G;
-  load_gauss(a.mean, a.scale, a.quat, a.dens, g, G);
   float gp[3] = {0.f, 0.f, 0.f}, gs[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f};
   float grho = 0.f;
-  const Rec3 r = rec[g];
-  const int cnt = box_count(unpack_box(r));
   const uint32_t off = offsets[g];
-  if (G.ok && cnt && (uint64_t)off + (uint64_t)cnt <= a.cap) {  // (beyond capacity: dropped)
+  const int cnt = (int)(offsets[g + 1] - off);
+  Gauss G;
+  G.ok = false;
+  if (cnt && (uint64_t)off + (uint64_t)cnt <= a.cap)  // (beyond capacity: dropped)
+    load_gauss(a.mean, a.scale, a.quat, a.dens, g, G);
+  if (!G.ok && accumulate) return;  // adds nothing
+  if (G.ok) {
     float S[10];
     for (int k = 0; k < 10; ++k) S[k] = 0.f;
     const float *sl = slots + (int64_t)off * 10;
@@ -665,11 +671,11 @@ __global__ __launch_bounds__(kBlock) void k_vox_chain(VoxArgs a, const Rec3 *__r
   if (g_dens) g_dens[g] = accumulate ? g_dens[g] + grho : grho;
 }
 
-void launch_vox_chain(const VoxArgs &a, const Rec3 *rec, const uint32_t *offsets,
-                      const float *slots, float *g_mean, float *g_scale, float *g_quat,
-                      float *g_dens, int accumulate, hipStream_t s) {
+void launch_vox_chain(const VoxArgs &a, const uint32_t *offsets, const float *slots,
+                      float *g_mean, float *g_scale, float *g_quat, float *g_dens, int accumulate,
+                      hipStream_t s) {
   unsigned nb = (unsigned)((a.M + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_vox_chain, dim3(nb), dim3(kBlock), 0, s, a, rec, offsets, slots, g_mean,
+  hipLaunchKernelGGL(k_vox_chain, dim3(nb), dim3(kBlock), 0, s, a, offsets, slots, g_mean,
                      g_scale, g_quat, g_dens, accumulate);
 }
 
