@@ -186,6 +186,25 @@ def test_signed_densities(ops):
     assert el <= 1.0 and nr <= 1.0
 
 
+def test_small_density_scale(ops):
+    """Densities near 1e-20 (log2|rho_hat| about -66): the forward's
+    multiplicative columns then need the form below about 34 over a
+    sub-tile, and their cutoff is compared on e = |rho_hat| exp2(...) itself;
+    image and gradients against the oracle, whose tolerances scale with the
+    image."""
+    g = scenes.random_scene(46, 300, lo=0.006, hi=0.1, box=0.5, rho=(-2e-20, 2e-20))
+    th = [1.1, 3.9]
+    views = ops.Views.cone(th, 13.64, 20.46, 80, 72, 0.045)
+    ov = [oracle.cone_view(t, 13.64, 20.46, 80, 72, 0.045) for t in th]
+    img, _ = _proj_fwd(ops, g, views)
+    v, _ = parity.forward_violation(img, oracle.project(g, ov))
+    _report("small densities forward", v)
+    assert v <= 1.0
+    el, nr = _check_proj_grad(ops, g, views, ov, 9)
+    _report("small densities grads", max(el, nr))
+    assert el <= 1.0 and nr <= 1.0
+
+
 def test_parallel_gradients(ops):
     from scipy.spatial.transform import Rotation
     g = scenes.random_scene(42, 200, lo=0.03, hi=0.12, box=0.6)
