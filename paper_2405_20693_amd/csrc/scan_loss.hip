@@ -132,22 +132,13 @@ constexpr int kIW = kSW + 2 * kR, kIH = kSH + 2 * kR;  // 42 x 42 input region
 constexpr int kRB = 4;                                  // outputs per thread per pass
 constexpr float kC1 = 0.0001f, kC2 = 0.0009f;
 
-__constant__ float c_win[kWin];
-
-static void init_window() {
-  static bool done = false;
-  if (done) return;
-  double g[kWin], s = 0.0;
-  for (int i = 0; i < kWin; ++i) {
-    double x = i - kR;
-    g[i] = exp(-x * x / (2.0 * 1.5 * 1.5));
-    s += g[i];
-  }
-  float f[kWin];
-  for (int i = 0; i < kWin; ++i) f[i] = (float)(g[i] / s);
-  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_win), f, sizeof(f));
-  done = true;
-}
+// The 11-tap Gaussian window (sigma 1.5) normalised to unit sum: weights
+// exp(-(i-5)^2 / 4.5) / sum, evaluated in double and rounded to float once.
+// Held as literals so that no call has to upload them (no per-device set-up,
+// nothing for a graph capture to record).
+__constant__ float c_win[kWin] = {
+    0x1.0d956cp-10f, 0x1.f1fe02p-8f, 0x1.26eb18p-5f, 0x1.bff0fep-4f, 0x1.b43c40p-3f, 0x1.106560p-2f,
+    0x1.b43c40p-3f,  0x1.bff0fep-4f, 0x1.26eb18p-5f, 0x1.f1fe02p-8f, 0x1.0d956cp-10f};
 
 int ssim_num_blocks(int n, int h, int w) {
   return n * ((h + kSH - 1) / kSH) * ((w + kSW - 1) / kSW);
@@ -271,7 +262,6 @@ __global__ __launch_bounds__(kBlock) void k_ssim_coeffs(const float *__restrict_
 
 void launch_ssim_coeffs(const float *x, const float *y, int n, int h, int w, float *coef,
                         float *partials, hipStream_t s) {
-  init_window();
   hipLaunchKernelGGL(k_ssim_coeffs, dim3(ssim_num_blocks(n, h, w)), dim3(kBlock), 0, s, x, y, n, h,
                      w, coef, partials);
 }
@@ -457,7 +447,6 @@ __global__ __launch_bounds__(kBlock) void k_ssim_fused(const float *__restrict__
 
 void launch_ssim_fused(const float *x, const float *y, int n, int h, int w, float lambda_ssim,
                        float *grad, float *partials, hipStream_t s) {
-  init_window();
   hipLaunchKernelGGL(k_ssim_fused, dim3(ssim_num_blocks(n, h, w)), dim3(kBlock), 0, s, x, y, n, h,
                      w, lambda_ssim, grad, partials);
 }
