@@ -211,6 +211,24 @@ GS_API gs_status gs_loss_image(const float *render, const float *measured, int32
                         int32_t w, float lambda_ssim, float *loss_out, float *grad, gs_plan *plan,
                         hipStream_t stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Computes
+ * exactly what gs_loss_image computes (same kernels, bitwise the same loss
+ * and gradient), without a plan: the per-tile partial sums go to a static
+ * device buffer inside the library, one per GPU, held until the process ends
+ * (2 MiB: GS_LOSS_IMAGE_NOALLOC_TILES tiles of 32 x 32 pixels).  A stack of
+ * more than that many tiles, n_img ceil(h/32) ceil(w/32), returns
+ * GS_EUNSUPPORTED before any launch.  The call makes no hipMalloc, hipFree or
+ * other allocating call; the first call on a device looks up that device's
+ * buffer address once.  Every call on one GPU shares its buffer: calls that
+ * overlap on one GPU (streams or threads with no ordering between them) race
+ * and their losses are undefined; calls ordered on one stream are safe.  The
+ * buffer needs no clearing: a call writes every partial sum it reads. */
+#define GS_LOSS_IMAGE_NOALLOC_TILES 262144
+GS_API gs_status gs_loss_image_noalloc(const float *render, const float *measured, int32_t n_img,
+                                       int32_t h, int32_t w, float lambda_ssim, float *loss_out,
+                                       float *grad, hipStream_t stream);
+
 /* 3D total variation of a block [nz][ny][nx] (Eq. 8 regularizer): the sum
  * over the three axes of the mean absolute forward difference.
  * loss_out (device, 1 float): the TV value (unweighted).

@@ -123,6 +123,8 @@ EXPORTS = {
                                        c_void_p]),
     "gs_loss_image": (ctypes.c_int, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_float,
                                      c_void_p, c_void_p, c_void_p, c_void_p]),
+    "gs_loss_image_noalloc": (ctypes.c_int, [c_void_p, c_void_p, c_int32, c_int32, c_int32,
+                                             c_float, c_void_p, c_void_p, c_void_p]),
     "gs_loss_tv": (ctypes.c_int, [c_void_p, c_int32, c_int32, c_int32, c_float, c_void_p, c_void_p,
                                   c_int32, c_void_p, c_void_p]),
     "gs_plan_set_timing": (ctypes.c_int, [c_void_p, c_int32]),

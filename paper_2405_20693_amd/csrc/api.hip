@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -537,6 +538,55 @@ gs_status vox_bin(gs_plan *pl, const gs_gaussians *g, const gs_grid *grid, float
   return GS_OK;
 }
 
+gs_status check_loss_image(const float *render, const float *measured, int32_t n_img, int32_t h,
+                           int32_t w, float lambda_ssim, const float *loss_out, int *nb) {
+  if (!render || !measured || !loss_out) return fail(GS_EINVAL, "NULL array argument");
+  if (n_img < 1 || h < 1 || w < 1) return fail(GS_EINVAL, "sizes must be >= 1");
+  if (!std::isfinite(lambda_ssim)) return fail(GS_EINVAL, "lambda_ssim not finite");
+  const int64_t tiles = (int64_t)n_img * ((h + 31) / 32) * ((w + 31) / 32);
+  if (tiles > 0x7fffffffLL) return fail(GS_EUNSUPPORTED, "more than 2^31-1 tiles of 32 x 32");
+  *nb = ssim_num_blocks(n_img, h, w);
+  return GS_OK;
+}
+
+// The SSIM + L1 kernel writes one pair of partial sums per 32 x 32 tile; the
+// finish kernel adds them in a fixed order.
+void launch_loss_image(const float *render, const float *measured, int n_img, int h, int w,
+                       float lambda_ssim, float *loss_out, float *grad, int nb, float *partials,
+                       hipStream_t s) {
+  if (grad)
+    launch_ssim_fused(render, measured, n_img, h, w, lambda_ssim, grad, partials, s);
+  else
+    launch_ssim_coeffs(render, measured, n_img, h, w, nullptr, partials, s);
+  launch_loss_finish(partials, nb, n_img, h, w, lambda_ssim, loss_out, s);
+}
+
+// Static scratch of gs_loss_image_noalloc: the per-tile partial sums, two
+// floats per tile.  Each device holds its own copy, whose address is looked
+// up once per device (the array's name is not a device address on the host).
+constexpr int kNoAllocLossTiles = GS_LOSS_IMAGE_NOALLOC_TILES;
+constexpr int kMaxNoAllocDevices = 64;
+static __device__ __align__(256) float scratch[2 * kNoAllocLossTiles];
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kMaxNoAllocDevices] = {};
+
+gs_status noalloc_scratch(float **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(GS_EHIP, "hipGetDevice failed");
+  if (dev < 0 || dev >= kMaxNoAllocDevices)
+    return fail(GS_EUNSUPPORTED, "device index beyond the static buffers' table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(GS_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<float *>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return GS_OK;
+}
+
 struct TempPlan {
   gs_plan *p = nullptr;
   bool owned = false;
@@ -968,21 +1018,30 @@ gs_status gs_voxelize_bwd(const gs_gaussians *g, const gs_grid *grid, float cuto
 gs_status gs_loss_image(const float *render, const float *measured, int32_t n_img, int32_t h,
                         int32_t w, float lambda_ssim, float *loss_out, float *grad, gs_plan *plan,
                         hipStream_t stream) {
-  if (!render || !measured || !loss_out) return fail(GS_EINVAL, "NULL array argument");
-  if (n_img < 1 || h < 1 || w < 1) return fail(GS_EINVAL, "sizes must be >= 1");
-  if (!std::isfinite(lambda_ssim)) return fail(GS_EINVAL, "lambda_ssim not finite");
+  int nb = 0;
+  GS_TRY(check_loss_image(render, measured, n_img, h, w, lambda_ssim, loss_out, &nb));
   if (!plan) return fail(GS_EINVAL, "plan is NULL");
   plan->used = true;
   plan->last_stream = stream;
-  const int nb = ssim_num_blocks(n_img, h, w);
   GS_TRY(ensure(plan, plan->l_part, 2 * sizeof(float) * (size_t)nb, stream));
   StageTimer t(plan, GS_STAGE_LOSS_IMAGE, stream);
-  if (grad)
-    launch_ssim_fused(render, measured, n_img, h, w, lambda_ssim, grad, P<float>(plan->l_part),
-                      stream);
-  else
-    launch_ssim_coeffs(render, measured, n_img, h, w, nullptr, P<float>(plan->l_part), stream);
-  launch_loss_finish(P<float>(plan->l_part), nb, n_img, h, w, lambda_ssim, loss_out, stream);
+  launch_loss_image(render, measured, n_img, h, w, lambda_ssim, loss_out, grad, nb,
+                    P<float>(plan->l_part), stream);
+  return check_launch("image loss");
+}
+
+gs_status gs_loss_image_noalloc(const float *render, const float *measured, int32_t n_img,
+                                int32_t h, int32_t w, float lambda_ssim, float *loss_out,
+                                float *grad, hipStream_t stream) {
+  int nb = 0;
+  GS_TRY(check_loss_image(render, measured, n_img, h, w, lambda_ssim, loss_out, &nb));
+  if (nb > kNoAllocLossTiles)
+    return fail(GS_EUNSUPPORTED, "n_img x ceil(h/32) x ceil(w/32) = " + std::to_string(nb) +
+                                     " tiles exceeds the " + std::to_string(kNoAllocLossTiles) +
+                                     " of the static buffer");
+  float *part = nullptr;
+  GS_TRY(noalloc_scratch(&part));
+  launch_loss_image(render, measured, n_img, h, w, lambda_ssim, loss_out, grad, nb, part, stream);
   return check_launch("image loss");
 }
 

@@ -245,6 +245,21 @@ def image_loss(render, measured, plan, lambda_ssim=0.25, grad=True, loss_out=Non
     return loss_out, (grad_out if grad else None)
 
 
+def image_loss_noalloc(render, measured, lambda_ssim=0.25, grad=True, loss_out=None,
+                       grad_out=None):
+    """image_loss through gs_loss_image_noalloc: no plan, and the library
+    allocates nothing (its partial sums live in a static per-GPU buffer)."""
+    n, h, w = render.shape
+    if loss_out is None:
+        loss_out = torch.empty(3, device=render.device, dtype=torch.float32)
+    if grad and grad_out is None:
+        grad_out = torch.empty_like(render)
+    N.call("gs_loss_image_noalloc", _dev(render, "render"), _dev(measured, "measured", (n, h, w)),
+           n, h, w, float(lambda_ssim), _dev(loss_out, "loss_out", (3,)),
+           _dev(grad_out, "grad_out", (n, h, w)) if grad else None, _stream())
+    return loss_out, (grad_out if grad else None)
+
+
 def tv_loss(volume, plan, weight=1.0, grad=True, accumulate=False, loss_out=None, grad_out=None):
     nz, ny, nx = volume.shape
     if loss_out is None:
