@@ -21,7 +21,8 @@
  *  - All GPU work is enqueued on `stream`; results are ready when the stream
  *    reaches that point.  The projection and voxelization forward passes read
  *    back one integer (the number of tile entries) and so synchronize `stream`
- *    once; everything else is asynchronous.
+ *    once, unless the plan is reserved (gs_plan_reserve); everything else is
+ *    asynchronous.
  *  - Ownership: the caller owns every input, output and gradient buffer; the
  *    library never frees caller memory.  A plan owns only its workspace, which
  *    it obtains through the allocator given at creation (hipMalloc if NULL) and
@@ -61,7 +62,8 @@ typedef enum {
   GS_OK = 0,
   GS_EINVAL = 1,        /* invalid argument (null pointer, bad size, bad geometry) */
   GS_ENOMEM = 2,        /* workspace allocation failed */
-  GS_EOVERFLOW = 3,     /* more than 2^32-1 tile entries in one call: use fewer views per call */
+  GS_EOVERFLOW = 3,     /* more than 2^32-1 tile entries in one call (use fewer views per call),
+                           or a reserved plan's call needed more entries than reserved */
   GS_EHIP = 4,          /* a HIP runtime call or kernel launch failed */
   GS_EUNSUPPORTED = 5   /* valid but unsupported request (e.g. detector wider than 16384) */
 } gs_status;
@@ -122,13 +124,18 @@ typedef struct gs_plan gs_plan;
  * device memory of the current device aligned to 256 bytes. */
 GS_API gs_status gs_plan_create(gs_alloc_fn alloc, gs_free_fn free_fn, void *ctx, gs_plan **out);
 
-/* Release the plan's workspace (after synchronizing the last stream it used). */
+/* Release the plan's workspace after synchronizing the last stream it used
+ * (only that stream: other streams of the device are not waited for).  A
+ * caller that used the plan on several streams orders them first. */
 GS_API void gs_plan_destroy(gs_plan *plan);
 
 /* Synchronize the plan's last stream and report the number of Gaussians (or
- * cone-beam (view, Gaussian) pairs) skipped by the last forward call and the
- * number of tile entries it produced (0 for a reserved plan: see
- * gs_plan_check).  Either pointer may be NULL. */
+ * cone-beam (view, Gaussian) pairs) skipped by the last forward call, and the
+ * number of tile entries the last projection and voxelization binnings of
+ * the plan needed (summed; for a reserved plan the entries needed, also when
+ * more than the reservation holds).  Either pointer may be NULL.  Returns
+ * GS_EOVERFLOW (outputs filled) while a reserved plan records a call that
+ * exceeded its reservation; gs_plan_check clears the record. */
 GS_API gs_status gs_plan_status(gs_plan *plan, int64_t *skipped, int64_t *tile_entries);
 
 /* Largest problem a reserved plan serves.  Zero counts skip that part. */
@@ -149,14 +156,20 @@ typedef struct {
  * so a caller can queue many calls ahead of the device or capture them in a
  * graph.  A call larger than the reservation fails with GS_EINVAL before any
  * launch.  If a call's tile lists exceed the reserved entries, the device
- * drops the excess entries (that call's results are incomplete) and records
- * it; gs_plan_check reports it. */
+ * drops the excess entries and records the overflow: that call's image or
+ * volume is incomplete and its backward writes no gradient (outputs
+ * undefined).  The record is visible to the host without synchronizing: once
+ * the device has set it, every projection or voxelization call on the plan
+ * returns GS_EOVERFLOW before any launch, and so do gs_plan_status and
+ * gs_plan_check (which synchronize), until gs_plan_check clears it.  Calls
+ * queued before the device set it still run. */
 GS_API gs_status gs_plan_reserve(gs_plan *plan, const gs_reserve *r, hipStream_t stream);
 
 /* For a reserved plan: synchronize its last stream, report the largest
  * projection and voxel entry counts any call needed since the previous check
- * (either pointer may be NULL) and return GS_EOVERFLOW if any call exceeded
- * the reservation since then.  Clears both records. */
+ * (either pointer may be NULL; filled also on GS_EOVERFLOW, so a caller can
+ * reserve again from them) and return GS_EOVERFLOW if any call exceeded the
+ * reservation since then.  Clears both records and the overflow state. */
 GS_API gs_status gs_plan_check(gs_plan *plan, int64_t *max_proj_entries, int64_t *max_vox_entries);
 
 /* (host) Fill a cone-beam view for gantry angle theta (radians) as in App. A,

@@ -79,6 +79,10 @@ struct gs_plan {
   unsigned long long *readback = nullptr;  // pinned, 4 entries
   // reserved mode: no allocation and no synchronization in the operator calls
   bool reserved = false;
+  // set by a scatter kernel whose call needed more entries than reserved
+  // (pinned, mapped, coherent host memory: the host reads it without any
+  // copy or synchronization); cleared by gs_plan_check
+  unsigned int *ovf_flag = nullptr, *ovf_flag_dev = nullptr;
   gs_reserve res{};
   // saved forward state
   bool p_valid = false, v_valid = false;
@@ -371,6 +375,7 @@ gs_status proj_bin(gs_plan *pl, const gs_gaussians *g, const gs_view *views, int
   }
   cutoff_consts(cutoff, a.kappa, a.thr, a.qmax);
   a.rectify = pl->rectify;
+  a.ovf_host = pl->reserved ? pl->ovf_flag_dev : nullptr;
   const int64_t VM = (int64_t)nv * a.M, VT = (int64_t)nv * a.T, VC = (int64_t)nv * a.C;
   if (VT + 1 > 0x7fffffffLL || VC + 1 > 0x7fffffffLL)
     return fail(GS_EUNSUPPORTED, "too many views in one call");
@@ -385,6 +390,7 @@ gs_status proj_bin(gs_plan *pl, const gs_gaussians *g, const gs_view *views, int
   GS_TRY(ensure(pl, pl->p_offsets, 4 * (VM + 1), s));  // + the slot total
   GS_TRY(ensure(pl, pl->p_totals, 16, s));
   GS_TRY(ensure_skipped(pl, s));
+  a.totals = P<unsigned long long>(pl->p_totals);
   StageTimer t_bin(pl, GS_STAGE_PROJ_BIN, s);
   launch_proj_hist(a, P<Rec2>(pl->p_rec), P<uint32_t>(pl->p_hist), P<uint32_t>(pl->p_chunk_cnt),
                    P<unsigned long long>(pl->skipped), s);
@@ -477,6 +483,7 @@ gs_status vox_bin(gs_plan *pl, const gs_gaussians *g, const gs_grid *grid, float
     a.bparts = tiles >= 1024 ? 1 : (int)std::min<int64_t>(16, (1024 + tiles - 1) / tiles);
   }
   cutoff_consts(cutoff, a.kappa, a.thr, a.qmax);
+  a.ovf_host = pl->reserved ? pl->ovf_flag_dev : nullptr;
   const int64_t GT = (int64_t)a.G * a.Tg, GC = (int64_t)a.G * a.C;
   const int64_t nb = (a.M + 4095) / 4096 + 1;
   GS_TRY(ensure(pl, pl->v_rec, sizeof(Rec3) * (size_t)a.M, s));
@@ -488,6 +495,7 @@ gs_status vox_bin(gs_plan *pl, const gs_gaussians *g, const gs_grid *grid, float
   GS_TRY(ensure(pl, pl->v_tile_start, 4 * (size_t)(GT + 1), s));
   GS_TRY(ensure(pl, pl->v_totals, 16, s));
   GS_TRY(ensure_skipped(pl, s));
+  a.totals = P<unsigned long long>(pl->v_totals);
   StageTimer t_bin(pl, GS_STAGE_VOX_BIN, s);
   launch_vox_records(a, P<Rec3>(pl->v_rec), P<uint32_t>(pl->v_count),
                      P<unsigned long long>(pl->skipped) + 1, s);
@@ -587,6 +595,17 @@ gs_status noalloc_scratch(float **out) {
   return GS_OK;
 }
 
+// A reserved plan whose device has reported an overflow refuses further
+// operator calls until gs_plan_check has reported and cleared it.  The flag
+// is read without synchronizing, so a call queued before the device set it
+// still runs (its chain kernels write nothing when it overflows itself).
+gs_status reserved_overflow(const gs_plan *pl) {
+  if (pl->reserved && pl->ovf_flag && *(volatile unsigned int *)pl->ovf_flag)
+    return fail(GS_EOVERFLOW, "an earlier call on this plan needed more tile entries than "
+                              "reserved; gs_plan_check reports and clears it");
+  return GS_OK;
+}
+
 struct TempPlan {
   gs_plan *p = nullptr;
   bool owned = false;
@@ -620,9 +639,20 @@ gs_status gs_plan_create(gs_alloc_fn alloc, gs_free_fn free_fn, void *ctx, gs_pl
     delete p;
     return fail(GS_EHIP, "pinned readback allocation failed");
   }
+  if (hipHostMalloc((void **)&p->ovf_flag, sizeof(unsigned int),
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+      hipHostGetDevicePointer((void **)&p->ovf_flag_dev, p->ovf_flag, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    if (p->ovf_flag) (void)hipHostFree(p->ovf_flag);
+    (void)hipHostFree(p->readback);
+    delete p;
+    return fail(GS_EHIP, "pinned overflow flag allocation failed");
+  }
+  *p->ovf_flag = 0u;
   for (int k = 0; k < gs_plan::kStageRing; ++k)
     if (hipEventCreateWithFlags(&p->stage_done[k], hipEventDisableTiming) != hipSuccess) {
       for (int j = 0; j < k; ++j) (void)hipEventDestroy(p->stage_done[j]);
+      (void)hipHostFree(p->ovf_flag);
       (void)hipHostFree(p->readback);
       delete p;
       return fail(GS_EHIP, "hipEventCreate failed");
@@ -633,8 +663,10 @@ gs_status gs_plan_create(gs_alloc_fn alloc, gs_free_fn free_fn, void *ctx, gs_pl
 
 void gs_plan_destroy(gs_plan *p) {
   if (!p) return;
-  if (p->used && p->last_stream != nullptr) (void)hipStreamSynchronize(p->last_stream);
-  if (p->used) (void)hipDeviceSynchronize();
+  // wait for the plan's own work only: its last stream and its view uploads
+  if (p->used) (void)hipStreamSynchronize(p->last_stream);
+  for (int k = 0; k < gs_plan::kStageRing; ++k)
+    if (p->stage_pending[k]) (void)hipEventSynchronize(p->stage_done[k]);
   Buf *bufs[] = {&p->p_views, &p->p_rec, &p->p_hist, &p->p_tile_total, &p->p_tile_start,
                  &p->p_chunk_cnt, &p->p_chunk_start, &p->p_offsets, &p->p_list, &p->p_slots,
                  &p->p_totals, &p->p_part, &p->p_scan_tmp, &p->p_fpart, &p->v_rec, &p->v_count, &p->v_offsets, &p->v_scan_tmp, &p->v_hist,
@@ -649,6 +681,7 @@ void gs_plan_destroy(gs_plan *p) {
     if (p->stage_done[k]) (void)hipEventDestroy(p->stage_done[k]);
   }
   if (p->readback) (void)hipHostFree(p->readback);
+  if (p->ovf_flag) (void)hipHostFree(p->ovf_flag);
   for (auto &t : p->timed) {
     (void)hipEventDestroy(t.a);
     (void)hipEventDestroy(t.b);
@@ -660,17 +693,38 @@ void gs_plan_destroy(gs_plan *p) {
 gs_status gs_plan_status(gs_plan *p, int64_t *skipped, int64_t *tile_entries) {
   if (!p) return fail(GS_EINVAL, "plan is NULL");
   if (skipped) *skipped = 0;
-  if (tile_entries && !p->reserved)
-    *tile_entries = (int64_t)(p->p_valid ? p->p_entries : 0) +
-                    (int64_t)(p->v_valid ? p->v_entries : 0);
-  else if (tile_entries)
-    *tile_entries = 0;
+  if (tile_entries) *tile_entries = 0;
   if (!p->used || !p->skipped.p) return GS_OK;
   GS_TRY(sync_stream(p, p->last_stream));
-  unsigned long long h[4] = {0, 0, 0, 0};
+  unsigned long long h[8] = {};
   if (hipMemcpy(h, p->skipped.p, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
     return fail(GS_EHIP, "status readback failed");
   if (skipped) *skipped = (int64_t)(h[2] + h[3]);
+  if (tile_entries) {
+    // entries the last binning of each operator needed (a reserved plan
+    // keeps at most its reservation, but counts them all)
+    int64_t e = 0;
+    if (p->reserved) {
+      unsigned long long t = 0;
+      if (p->p_valid && p->p_totals.p) {
+        if (hipMemcpy(&t, p->p_totals.p, 8, hipMemcpyDeviceToHost) != hipSuccess)
+          return fail(GS_EHIP, "status readback failed");
+        e += (int64_t)t;
+      }
+      if (p->v_valid && p->v_totals.p) {
+        if (hipMemcpy(&t, p->v_totals.p, 8, hipMemcpyDeviceToHost) != hipSuccess)
+          return fail(GS_EHIP, "status readback failed");
+        e += (int64_t)t;
+      }
+    } else {
+      e = (int64_t)(p->p_valid ? p->p_entries : 0) + (int64_t)(p->v_valid ? p->v_entries : 0);
+    }
+    *tile_entries = e;
+  }
+  if (p->reserved && (h[6] || h[7]))
+    return fail(GS_EOVERFLOW, std::to_string(h[6] + h[7]) +
+                                  " call(s) needed more tile entries than reserved; "
+                                  "gs_plan_check reports and clears it");
   return GS_OK;
 }
 
@@ -772,6 +826,7 @@ gs_status gs_plan_check(gs_plan *p, int64_t *max_proj_entries, int64_t *max_vox_
   if (max_vox_entries) *max_vox_entries = (int64_t)h[5];
   if (hipMemset(reinterpret_cast<unsigned long long *>(p->skipped.p) + 4, 0, 32) != hipSuccess)
     return fail(GS_EHIP, "check reset failed");
+  *(volatile unsigned int *)p->ovf_flag = 0u;
   if (h[6] || h[7])
     return fail(GS_EOVERFLOW, std::to_string(h[6] + h[7]) +
                                   " call(s) needed more tile entries than reserved");
@@ -870,6 +925,7 @@ gs_status gs_project_fwd(const gs_gaussians *g, const gs_view *views, int32_t n_
     tp.owned = true;
     plan = tp.p;
   }
+  GS_TRY(reserved_overflow(plan));
   plan->used = true;
   plan->last_stream = stream;
   const size_t pix = (size_t)n_views * views[0].width * views[0].height;
@@ -906,6 +962,7 @@ static gs_status project_bwd(const gs_gaussians *g, const gs_view *views, int32_
   if (!grad_image) return fail(GS_EINVAL, "grad_image is NULL");
   if (!grads) return fail(GS_EINVAL, "grads is NULL");
   if (!plan) return fail(GS_EINVAL, "plan is NULL");
+  GS_TRY(reserved_overflow(plan));
   plan->used = true;
   plan->last_stream = stream;
   if (g->n == 0) return GS_OK;
@@ -958,6 +1015,7 @@ gs_status gs_voxelize_fwd(const gs_gaussians *g, const gs_grid *grid, float cuto
     tp.owned = true;
     plan = tp.p;
   }
+  GS_TRY(reserved_overflow(plan));
   plan->used = true;
   plan->last_stream = stream;
   const size_t nvox = (size_t)grid->nx * grid->ny * grid->nz;
@@ -994,6 +1052,7 @@ gs_status gs_voxelize_bwd(const gs_gaussians *g, const gs_grid *grid, float cuto
   if (!grad_volume) return fail(GS_EINVAL, "grad_volume is NULL");
   if (!grads) return fail(GS_EINVAL, "grads is NULL");
   if (!plan) return fail(GS_EINVAL, "plan is NULL");
+  GS_TRY(reserved_overflow(plan));
   plan->used = true;
   plan->last_stream = stream;
   if (g->n == 0) return GS_OK;
@@ -1089,6 +1148,20 @@ double softplus_inv_d(double y) { return y > 30.0 ? y : std::log(std::expm1(y));
 
 gs_status gs_adam_step(const gs_params *p, int64_t n, const gs_grads *grads,
                        const gs_adam_config *cfg, hipStream_t stream) {
+  return gsk::adam_step_guarded(p, n, grads, cfg, nullptr, nullptr, stream);
+}
+
+}  // extern "C"
+
+namespace gsk {
+
+const unsigned long long *plan_control_words(const gs_plan *p) {
+  return p ? reinterpret_cast<const unsigned long long *>(p->skipped.p) : nullptr;
+}
+
+gs_status adam_step_guarded(const gs_params *p, int64_t n, const gs_grads *grads,
+                            const gs_adam_config *cfg, const gs_plan *g0, const gs_plan *g1,
+                            hipStream_t stream) {
   GS_TRY(check_params(p, true));
   if (!grads || !cfg) return fail(GS_EINVAL, "grads or cfg is NULL");
   if (n < 0) return fail(GS_EINVAL, "n < 0");
@@ -1117,9 +1190,15 @@ gs_status gs_adam_step(const gs_params *p, int64_t n, const gs_grads *grads,
   a.eps = 1e-15f;
   a.bc1_inv = (float)(1.0 / (1.0 - std::pow(b1, cfg->step)));
   a.bc2_inv = (float)(1.0 / (1.0 - std::pow(b2, cfg->step)));
+  a.guard[0] = plan_control_words(g0);
+  a.guard[1] = plan_control_words(g1);
   launch_adam(a, stream);
   return check_launch("adam step");
 }
+
+}  // namespace gsk
+
+extern "C" {
 
 gs_status gs_random_normals(uint64_t seed, uint64_t counter, int64_t n, float *out,
                             hipStream_t stream) {

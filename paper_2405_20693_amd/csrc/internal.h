@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/gs_train.h"
+
 namespace gsk {
 
 constexpr float kLog2e = 1.4426950408889634f;
@@ -295,6 +297,47 @@ __device__ inline void list_part(uint32_t b, uint32_t e, int part, int parts, ui
   pe = min(e, b + 64 * b1);
 }
 
+// ---------------------------------------------------- scan primitives --
+
+__device__ inline uint32_t wave_incl_scan(uint32_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
+// Exclusive scan over a 256-thread workgroup; all threads must call it.
+__device__ inline uint32_t block_excl_scan(uint32_t x, uint32_t *sh4, uint32_t &total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t inc = wave_incl_scan(x);
+  if (lane == 63) sh4[w] = inc;
+  __syncthreads();
+  uint32_t pre = 0;
+  for (int i = 0; i < w; ++i) pre += sh4[i];
+  total = sh4[0] + sh4[1] + sh4[2] + sh4[3];
+  __syncthreads();
+  return pre + inc - x;
+}
+
+__device__ inline uint32_t block_sum(uint32_t x, uint32_t *sh4) {
+  uint32_t t;
+  block_excl_scan(x, sh4, t);
+  return t;
+}
+
+// The last j in [0, 256) with off[j] <= e, off non-decreasing (for e < off[256],
+// Gaussian j is the one whose entries hold entry e).
+__device__ inline int entry_owner(const uint32_t *off, uint32_t e) {
+  int j = 0;
+#pragma unroll
+  for (int step = kBlock / 2; step > 0; step >>= 1)
+    if (off[j + step] <= e) j += step;
+  return j;
+}
+
 // ------------------------------------------------------------ launchers --
 
 struct ProjArgs {
@@ -309,6 +352,8 @@ struct ProjArgs {
   int cpt;                        // Gaussians per thread per binning chunk (chunk = kBlock * cpt)
   int parts;                      // workgroups per tile list in the render kernels (>= 1)
   uint32_t cap;                   // tile-list entries the list and slot buffers hold
+  const unsigned long long *totals;  // totals[0]: entries this call needs (> cap: overflow)
+  unsigned int *ovf_host;         // host-visible overflow flag of the plan (reserved plans), or null
 };
 
 void launch_mean_mu(const ProjArgs &a, float *mu_out, float *density_out, hipStream_t s);
@@ -324,7 +369,9 @@ void launch_scan2(const uint32_t *in0, uint32_t *out0, int n0, const uint32_t *i
 // 4, 5 the largest entry count since the last check; 6, 7 the number of calls
 // whose entries exceeded the capacity since then.  The projection scatter
 // moves 0 to 2, clears 0 and records 4 and 6 from totals[0]; entries at
-// positions >= a.cap are dropped.
+// positions >= a.cap are dropped, the host-visible flag a.ovf_host is set,
+// and the chain kernels of that call write nothing (their slots would be
+// incomplete).
 void launch_proj_scatter(const ProjArgs &a, const Rec2 *rec, const uint32_t *hist,
                          const uint32_t *tile_start, const uint32_t *chunk_start, uint2 *list,
                          uint32_t *offsets, unsigned long long *ctl,
@@ -366,6 +413,8 @@ struct VoxArgs {
   int parts;               // workgroups per tile list in the forward (>= 1)
   int bparts;              // and in the backward (its per-batch setup favours fewer parts)
   uint32_t cap;            // tile-list entries the list and slot buffers hold
+  const unsigned long long *totals;  // totals[0]: entries this call needs (> cap: overflow)
+  unsigned int *ovf_host;  // host-visible overflow flag of the plan (reserved plans), or null
 };
 
 void launch_vox_records(const VoxArgs &a, Rec3 *rec, uint32_t *count,
@@ -405,6 +454,13 @@ int tv_num_blocks(int nx, int ny, int nz);
 
 // Sets the message gs_last_error returns (for errors found outside api.hip).
 void set_last_error(const char *msg);
+// A plan's device control words (layout above), or null before its first call.
+const unsigned long long *plan_control_words(const gs_plan *p);
+// gs_adam_step that does nothing on the device when plan g0 or g1 (either may
+// be null) records a call that overflowed its reservation since its last check.
+gs_status adam_step_guarded(const gs_params *p, int64_t n, const gs_grads *grads,
+                            const gs_adam_config *cfg, const gs_plan *g0, const gs_plan *g1,
+                            hipStream_t stream);
 
 struct AdamArgs {
   float *raw[4];         // mean, log_scale, quat, density_raw
@@ -415,6 +471,9 @@ struct AdamArgs {
   float lr[4];
   float beta1, beta2, omb1, omb2;  // beta and 1 - beta, each rounded once from double
   float eps, bc1_inv, bc2_inv;
+  // control words of up to two plans (or null): the step does nothing if
+  // either records an overflowing call since its last gs_plan_check
+  const unsigned long long *guard[2];
 };
 void launch_adam(const AdamArgs &a, hipStream_t s);
 void launch_random_normals(uint64_t seed, uint64_t counter, int64_t n, float *out, hipStream_t s);

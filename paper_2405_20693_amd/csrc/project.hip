@@ -5,37 +5,6 @@
 
 namespace gsk {
 
-// ----------------------------------------------------------- primitives --
-
-__device__ inline uint32_t wave_incl_scan(uint32_t x) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t y = __shfl_up(x, d, 64);
-    if (lane >= d) x += y;
-  }
-  return x;
-}
-
-// Exclusive scan over a 256-thread workgroup; all threads must call it.
-__device__ inline uint32_t block_excl_scan(uint32_t x, uint32_t *sh4, uint32_t &total) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  uint32_t inc = wave_incl_scan(x);
-  if (lane == 63) sh4[w] = inc;
-  __syncthreads();
-  uint32_t pre = 0;
-  for (int i = 0; i < w; ++i) pre += sh4[i];
-  total = sh4[0] + sh4[1] + sh4[2] + sh4[3];
-  __syncthreads();
-  return pre + inc - x;
-}
-
-__device__ inline uint32_t block_sum(uint32_t x, uint32_t *sh4) {
-  uint32_t t;
-  block_excl_scan(x, sh4, t);
-  return t;
-}
-
 // --------------------------------------------------------- projection ----
 
 // Record (pixel units) and tile rectangle of one projected Gaussian.
@@ -210,14 +179,27 @@ void launch_hist_colscan(int groups, int C, int T, uint32_t *hist, uint32_t *til
                      groups, C, T, hist, tile_total);
 }
 
-// Grid (C, V).  Writes each Gaussian's tile entries at its tiles' cursors and
-// the base index of its backward slots (Gaussian order within the chunk).
-// Lanes take entries, not Gaussians: after the scan of the 256 Gaussians'
-// entry counts, lane i handles entries i, i + 256, ... and finds its Gaussian
-// by binary search of the staged offsets, so Gaussians covering many tiles
-// do not idle the rest of their wave.  Each entry carries the mask of the
-// tile's 8x8 sub-tiles that the cutoff ellipse meets (exact minimum of the
-// quadratic form over each sub-tile's pixel-centre rectangle).
+// Grid (C, V).  Writes each Gaussian's tile entries and the base index of
+// its backward slots (Gaussian order within the chunk).  The placement is a
+// stable counting sort: a chunk's entries of one tile sit in Gaussian order at
+// the tile's cursor, so every tile list is sorted by Gaussian index and any
+// two runs of the binning give the same lists (the forward's sums then run in
+// a fixed order).  Lanes take entries, not Gaussians: after the scan of the
+// 256 Gaussians' entry counts, an entry finds its Gaussian by binary search of
+// the staged offsets, so Gaussians covering many tiles do not idle the rest
+// of their wave.  Entries are placed in rounds of at most 256 entries from at
+// most 64 consecutive Gaussians: each entry sets its Gaussian's bit (index
+// within the round) in its tile's 64-bit LDS mask; after a barrier its
+// position is the tile's cursor plus the number of lower bits set, and the
+// entry holding the highest bit then advances the cursor and clears the mask.
+// Tiles are handled in windows of kScatterWindow so that masks and cursors
+// fit LDS.  Each entry carries the mask of the tile's 8x8 sub-tiles that the
+// cutoff ellipse meets (exact minimum of the quadratic form over each
+// sub-tile's pixel-centre rectangle).
+constexpr int kScatterWindow = 4096;
+
+int proj_scatter_lds(int T) { return min(T, kScatterWindow) * 12; }
+
 __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 *__restrict__ rec,
                                                          const uint32_t *__restrict__ hist,
                                                          const uint32_t *__restrict__ tile_start,
@@ -226,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
                                                          uint32_t *__restrict__ offsets,
                                                          unsigned long long *ctl,
                                                          const unsigned long long *totals) {
-  extern __shared__ uint32_t cur[];
+  extern __shared__ unsigned long long s_dyn[];  // window masks, then cursors
   __shared__ uint32_t sh4[4];
   __shared__ uint32_t s_off[kBlock + 1];  // exclusive entry offsets of the 256 Gaussians
   __shared__ uint32_t s_org[kBlock];      // rectangle origin tx0 | ty0 << 16
@@ -234,75 +216,112 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
   __shared__ float s_pu[kBlock], s_pv[kBlock], s_fa[kBlock], s_fb[kBlock], s_fc[kBlock];
   __shared__ float s_ia[kBlock], s_ic[kBlock];
   const int c = blockIdx.x, v = blockIdx.y, tid = threadIdx.x;
+  const int Tw = min(a.T, kScatterWindow);
+  unsigned long long *s_mask = s_dyn;
+  uint32_t *cur = reinterpret_cast<uint32_t *>(s_dyn + Tw);
   if (c == 0 && v == 0 && tid == 0) {  // the binning kernels of this call have finished
     ctl[2] = ctl[0];
     ctl[0] = 0ull;
     const unsigned long long e = totals[0];
     atomicMax(&ctl[4], e);
-    if (e > a.cap) atomicAdd(&ctl[6], 1ull);
+    if (e > a.cap) {
+      atomicAdd(&ctl[6], 1ull);
+      if (a.ovf_host) *(volatile unsigned int *)a.ovf_host = 1u;
+    }
   }
   const uint32_t *h = hist + ((int64_t)v * a.C + c) * a.T;
   const uint32_t *ts = tile_start + (int64_t)v * a.T;
-  for (int t = tid; t < a.T; t += kBlock) cur[t] = ts[t] + h[t];
-  uint32_t base = chunk_start[v * a.C + c];
   const int64_t g0 = (int64_t)c * kBlock * a.cpt;
-  for (int k = 0; k < a.cpt; ++k) {
-    int64_t gk = g0 + (int64_t)k * kBlock;
-    if (gk >= a.M) break;
-    int64_t g = gk + tid;
-    bool valid = g < a.M;
-    Rect2 rc{1, 0, 0, 0};
-    Rec2 r{};
-    if (valid) {
-      r = rec[(int64_t)v * a.M + g];
-      rc = unpack_rect(r.r0, r.r1);
+  uint32_t base = 0;
+  for (int w0 = 0; w0 < a.T; w0 += Tw) {
+    const int wn = min(Tw, a.T - w0);
+    for (int t = tid; t < wn; t += kBlock) {
+      cur[t] = ts[w0 + t] + h[w0 + t];
+      s_mask[t] = 0ull;
     }
-    int n = valid ? rect_count(rc) : 0;
-    uint32_t total;
-    uint32_t ex = block_excl_scan((uint32_t)n, sh4, total);  // synchronizes the workgroup
-    if (valid) offsets[(int64_t)v * a.M + g] = base + ex;
-    s_off[tid] = ex;
-    if (tid == 0) s_off[kBlock] = total;
-    s_org[tid] = (uint32_t)rc.x0 | ((uint32_t)rc.y0 << 16);
-    s_w[tid] = (float)(rc.x1 - rc.x0 + 1);
-    s_pu[tid] = r.pu;
-    s_pv[tid] = r.pv;
-    s_fa[tid] = -r.c00;
-    s_fb[tid] = -r.c01;
-    s_fc[tid] = -r.c11;
-    s_ia[tid] = -0.5f / r.c00;
-    s_ic[tid] = -0.5f / r.c11;
-    __syncthreads();
-    for (uint32_t e = (uint32_t)tid; e < total; e += kBlock) {
-      int j = 0;  // the last Gaussian whose offset is <= e (it has entries)
-#pragma unroll
-      for (int step = kBlock / 2; step > 0; step >>= 1)
-        if (s_off[j + step] <= e) j += step;
-      const uint32_t kin = e - s_off[j];
-      const float wf = s_w[j];
-      int ry = (int)__fdividef((float)kin, wf);  // row within the rectangle, corrected below
-      const int wi = (int)wf;
-      if ((uint32_t)((ry + 1) * wi) <= kin) ++ry;
-      if ((uint32_t)(ry * wi) > kin) --ry;
-      const int rx = (int)kin - ry * wi;
-      const uint32_t org = s_org[j];
-      const int tx = (int)(org & 0xffffu) + rx, ty = (int)(org >> 16) + ry;
-      const float pu = s_pu[j], pv = s_pv[j], fa = s_fa[j], fb = s_fb[j], fc = s_fc[j];
-      const float ia = s_ia[j], ic = s_ic[j];
-      uint32_t m = 0;
-#pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        const int sx = tx * kTile + (w & 1) * kSub, sy = ty * kTile + (w >> 1) * kSub;
-        const float f = rect_min_form(fa, fb, fc, ia, ic, (float)sx - pu, (float)(sx + kSub - 1) - pu,
-                                      (float)sy - pv, (float)(sy + kSub - 1) - pv);
-        m |= (f <= a.qmax ? 1u : 0u) << w;
+    base = chunk_start[v * a.C + c];
+    for (int k = 0; k < a.cpt; ++k) {
+      const int64_t gk = g0 + (int64_t)k * kBlock;
+      if (gk >= a.M) break;
+      const int64_t g = gk + tid;
+      const bool valid = g < a.M;
+      Rect2 rc{1, 0, 0, 0};
+      Rec2 r{};
+      if (valid) {
+        r = rec[(int64_t)v * a.M + g];
+        rc = unpack_rect(r.r0, r.r1);
       }
-      const uint32_t pos = atomicAdd(&cur[ty * a.TX + tx], 1u);
-      if (pos < a.cap)
-        list[pos] = make_uint2((uint32_t)(gk + j) | (m << kEntryMaskShift), base + e);
+      const int n = valid ? rect_count(rc) : 0;
+      uint32_t total;
+      const uint32_t ex = block_excl_scan((uint32_t)n, sh4, total);  // synchronizes the workgroup
+      if (valid && w0 == 0) offsets[(int64_t)v * a.M + g] = base + ex;
+      s_off[tid] = ex;
+      if (tid == 0) s_off[kBlock] = total;
+      s_org[tid] = (uint32_t)rc.x0 | ((uint32_t)rc.y0 << 16);
+      s_w[tid] = (float)(rc.x1 - rc.x0 + 1);
+      s_pu[tid] = r.pu;
+      s_pv[tid] = r.pv;
+      s_fa[tid] = -r.c00;
+      s_fb[tid] = -r.c01;
+      s_fc[tid] = -r.c11;
+      s_ia[tid] = -0.5f / r.c00;
+      s_ic[tid] = -0.5f / r.c11;
+      __syncthreads();
+      for (uint32_t r0 = 0; r0 < total;) {
+        const int jA = entry_owner(s_off, r0);  // first Gaussian of the round (uniform)
+        const uint32_t r1 = min(r0 + (uint32_t)kBlock, s_off[min(jA + 64, kBlock)]);
+        const uint32_t e = r0 + (uint32_t)tid;
+        int t = 0, bit = 0;
+        bool act = false;
+        uint2 ent;
+        if (e < r1) {
+          const int j = entry_owner(s_off, e);
+          const uint32_t kin = e - s_off[j];
+          const float wf = s_w[j];
+          int ry = (int)__fdividef((float)kin, wf);  // row within the rectangle, corrected below
+          const int wi = (int)wf;
+          if ((uint32_t)((ry + 1) * wi) <= kin) ++ry;
+          if ((uint32_t)(ry * wi) > kin) --ry;
+          const int rx = (int)kin - ry * wi;
+          const uint32_t org = s_org[j];
+          const int tx = (int)(org & 0xffffu) + rx, ty = (int)(org >> 16) + ry;
+          t = ty * a.TX + tx - w0;
+          act = t >= 0 && t < wn;
+          if (act) {
+            const float pu = s_pu[j], pv = s_pv[j], fa = s_fa[j], fb = s_fb[j], fc = s_fc[j];
+            const float ia = s_ia[j], ic = s_ic[j];
+            uint32_t m = 0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+              const int sx = tx * kTile + (w & 1) * kSub, sy = ty * kTile + (w >> 1) * kSub;
+              const float f = rect_min_form(fa, fb, fc, ia, ic, (float)sx - pu,
+                                            (float)(sx + kSub - 1) - pu, (float)sy - pv,
+                                            (float)(sy + kSub - 1) - pv);
+              m |= (f <= a.qmax ? 1u : 0u) << w;
+            }
+            ent = make_uint2((uint32_t)(gk + j) | (m << kEntryMaskShift), base + e);
+            bit = j - jA;
+            atomicOr(&s_mask[t], 1ull << bit);
+          }
+        }
+        __syncthreads();
+        unsigned long long mk = 0ull;
+        if (act) {
+          mk = s_mask[t];
+          const uint32_t pos = cur[t] + (uint32_t)__popcll(mk & ((1ull << bit) - 1ull));
+          if (pos < a.cap) list[pos] = ent;
+        }
+        __syncthreads();
+        if (act && (mk >> bit) == 1ull) {  // the round's last entry of this tile
+          cur[t] += (uint32_t)__popcll(mk);
+          s_mask[t] = 0ull;
+        }
+        __syncthreads();
+        r0 = r1;
+      }
+      base += total;
+      __syncthreads();  // the next batch restages
     }
-    base += total;
-    __syncthreads();  // the next batch restages
   }
   // the slot total closes the offsets array (offsets[V M]); the last chunk of
   // the last view ends there
@@ -314,7 +333,7 @@ void launch_proj_scatter(const ProjArgs &a, const Rec2 *rec, const uint32_t *his
                          uint32_t *offsets, unsigned long long *ctl,
                          const unsigned long long *totals, hipStream_t s) {
   dim3 grid(a.C, a.V);
-  hipLaunchKernelGGL(k_proj_scatter, grid, dim3(kBlock), a.T * sizeof(uint32_t), s, a, rec, hist,
+  hipLaunchKernelGGL(k_proj_scatter, grid, dim3(kBlock), proj_scatter_lds(a.T), s, a, rec, hist,
                      tile_start, chunk_start, list, offsets, ctl, totals);
 }
 
@@ -756,6 +775,7 @@ __global__ __launch_bounds__(kBlock) void k_proj_chain(ProjArgs a,
                                                        const float *__restrict__ slots,
                                                        float *__restrict__ part, int stats) {
   __shared__ float4 s_st[4][kChainStage];
+  if (*a.totals > a.cap) return;  // the call overflowed its reservation: slots are incomplete
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const bool active = g < a.M;
@@ -926,7 +946,7 @@ __global__ __launch_bounds__(kBlock) void k_proj_chain_reduce(ProjArgs a, int n_
                                                               float *g_quat, float *g_dens,
                                                               int accumulate, ChainStats st) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (g >= a.M) return;
+  if (g >= a.M || *a.totals > a.cap) return;
   const int stats = st.ndc_sum != nullptr;
   const int n_parts = kChainParts + (stats ? 2 : 0);
   float sum[kChainParts + 2];

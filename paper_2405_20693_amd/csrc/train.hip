@@ -31,6 +31,10 @@ __device__ inline void segment_of(int64_t e, int64_t n, int &seg, int64_t &i) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_adam(AdamArgs a) {
+  // a guarded step is skipped when a guarding plan recorded a call that
+  // overflowed its reservation (its gradients are incomplete)
+  for (int k = 0; k < 2; ++k)
+    if (a.guard[k] && (a.guard[k][6] | a.guard[k][7])) return;
   const int64_t total = 11 * a.n;
   for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * kBlock) {

@@ -201,18 +201,31 @@ gs_status reserve_plans(gs_trainer *t, int64_t proj_entries, int64_t vox_entries
   return GS_OK;
 }
 
-// At a synchronization point: fail if an iteration exceeded the reserved
-// tile lists; grow the reservation when the largest need passed half of it
-// or the parameter capacity grew.
+// At a synchronization point: grow the reservation when the largest need
+// since the last check passed half of it, exceeded it, or the parameter
+// capacity grew, then fail if an iteration exceeded the reserved tile lists.
+// Such iterations changed no parameter (their Adam steps are guarded on the
+// plans' overflow records), and the grown reservation lets a new run go on.
 gs_status check_plans(gs_trainer *t) {
   if (!t->reserved) return GS_OK;
   int64_t pe = 0, ve = 0, unused = 0;
-  TR_TRY(gs_plan_check(t->proj, &pe, &unused));
-  if (t->cfg.lambda_tv > 0.f && t->cfg.tv_size > 0) TR_TRY(gs_plan_check(t->vox, &unused, &ve));
+  const gs_status sp = gs_plan_check(t->proj, &pe, &unused);
+  if (sp != GS_OK && sp != GS_EOVERFLOW) return sp;
+  gs_status sv = GS_OK;
+  if (t->cfg.lambda_tv > 0.f && t->cfg.tv_size > 0) {
+    sv = gs_plan_check(t->vox, &unused, &ve);
+    if (sv != GS_OK && sv != GS_EOVERFLOW) return sv;
+  }
   const int64_t cap = std::max(t->sets[0].cap, t->sets[1].cap);
   (void)ve;
-  if (2 * pe > t->res_proj_entries || cap > t->res_gaussians)
-    return reserve_plans(t, std::max(pe, t->res_proj_entries / 3), 0);
+  const bool over = sp == GS_EOVERFLOW || sv == GS_EOVERFLOW;
+  if (over || 2 * pe > t->res_proj_entries || cap > t->res_gaussians)
+    TR_TRY(reserve_plans(t, std::max(pe, t->res_proj_entries / 3), 0));
+  if (over) {
+    gsk::set_last_error("iterations needed more tile entries than reserved: their parameter "
+                        "updates were skipped and the reservation has grown; run again");
+    return GS_EOVERFLOW;
+  }
   return GS_OK;
 }
 
@@ -312,7 +325,8 @@ gs_status step(gs_trainer *t, const int32_t *view_idx, const int32_t *tv_offset,
   const double f = std::pow((double)c.lr_final_ratio, (double)t->iter / (double)c.iterations);
   gs_adam_config ac{(float)(c.lr_mean * f), (float)(c.lr_scale * f), (float)(c.lr_quat * f),
                     (float)(c.lr_density * f), it1};
-  TR_TRY(gs_adam_step(&t->sets[t->cur].p, t->n, &gr, &ac, t->stream));
+  TR_TRY(gsk::adam_step_guarded(&t->sets[t->cur].p, t->n, &gr, &ac, t->reserved ? t->proj : nullptr,
+                                 t->reserved && tv ? t->vox : nullptr, t->stream));
   t->iter = it1;
   if (densify_due(c, it1)) {
     TR_TRY(densify(t, normals));
@@ -436,7 +450,12 @@ gs_status gs_trainer_step(gs_trainer *t, const int32_t *view_idx, const int32_t 
     return GS_EINVAL;
   TR_TRY(grow(t->loss_dev, t->loss_cap, 4));
   const int32_t zero3[3] = {0, 0, 0};
-  TR_TRY(step(t, view_idx, tv_offset ? tv_offset : zero3, normals, t->loss_dev));
+  const gs_status st = step(t, view_idx, tv_offset ? tv_offset : zero3, normals, t->loss_dev);
+  if (st == GS_EOVERFLOW) {  // a plan refused the call: grow the reservation and report
+    const gs_status c = check_plans(t);
+    return c == GS_OK ? GS_EOVERFLOW : c;
+  }
+  TR_TRY(st);
   if (loss) {
     float h[4];
     if (hipMemcpyAsync(h, t->loss_dev, sizeof(h), hipMemcpyDeviceToHost, t->stream) != hipSuccess ||
@@ -477,7 +496,12 @@ gs_status gs_trainer_run(gs_trainer *t, int32_t iters, float *losses) {
       TR_TRY(gs_random_normals(c.seed, (uint64_t)t->iter, (int64_t)nz, t->normals, t->stream));
       nrm = t->normals;
     }
-    TR_TRY(step(t, idx.data(), off, nrm, t->loss_dev + 4 * (size_t)k));
+    const gs_status st = step(t, idx.data(), off, nrm, t->loss_dev + 4 * (size_t)k);
+    if (st == GS_EOVERFLOW) {  // a plan refused the call: grow the reservation and report
+      const gs_status c = check_plans(t);
+      return c == GS_OK ? GS_EOVERFLOW : c;
+    }
+    TR_TRY(st);
   }
   TR_TRY(check_plans(t));
   if (losses) {

@@ -111,46 +111,128 @@ void launch_vox_hist(const VoxArgs &a, const Rec3 *rec, uint32_t *hist, hipStrea
                      hist);
 }
 
+// Grid (C, G).  Writes the chunk's entries of the group's tiles as a stable
+// counting sort, like the projection scatter: a chunk's entries of one tile
+// sit in Gaussian order at the tile's cursor, so tile lists are sorted by
+// Gaussian index and the same in every run.  Per batch of 256 Gaussians the
+// entry counts (boxes clipped to the group's tile layers) are scanned, and
+// lanes take entries in rounds of at most 256 entries from at most 64
+// consecutive Gaussians, ranked by 64-bit LDS masks per tile (the bit of the
+// Gaussian within the round; position = cursor + lower bits set).  Tiles are
+// handled in windows of kVoxScatterWindow so that masks and cursors fit LDS.
+constexpr int kVoxScatterWindow = 4096;
+
+int vox_scatter_lds(int Tg) { return min(Tg, kVoxScatterWindow) * 12; }
+
 __global__ __launch_bounds__(kBlock) void k_vox_scatter(VoxArgs a, const Rec3 *__restrict__ rec,
                                                         const uint32_t *__restrict__ hist,
                                                         const uint32_t *__restrict__ tile_start,
                                                         uint32_t *__restrict__ list,
                                                         unsigned long long *ctl,
                                                         const unsigned long long *totals) {
-  extern __shared__ uint32_t cur[];
+  extern __shared__ unsigned long long s_dyn[];  // window masks, then cursors
+  __shared__ uint32_t sh4[4];
+  __shared__ uint32_t s_off[kBlock + 1];
+  __shared__ uint32_t s_org[kBlock];  // box origin in tiles: x0 | y0 << 16
+  __shared__ uint32_t s_z0[kBlock];   // first tile layer of the box within the group
+  __shared__ uint32_t s_dim[kBlock];  // box extent in tiles: bx | by << 16
   const int c = blockIdx.x, grp = blockIdx.y, tid = threadIdx.x;
+  const int Tw = min(a.Tg, kVoxScatterWindow);
+  unsigned long long *s_mask = s_dyn;
+  uint32_t *cur = reinterpret_cast<uint32_t *>(s_dyn + Tw);
   if (c == 0 && grp == 0 && tid == 0) {  // the binning kernels of this call have finished
     ctl[3] = ctl[1];
     ctl[1] = 0ull;
     const unsigned long long e = totals[0];
     atomicMax(&ctl[5], e);
-    if (e > a.cap) atomicAdd(&ctl[7], 1ull);
+    if (e > a.cap) {
+      atomicAdd(&ctl[7], 1ull);
+      if (a.ovf_host) *(volatile unsigned int *)a.ovf_host = 1u;
+    }
   }
   const uint32_t *hp = hist + ((int64_t)grp * a.C + c) * a.Tg;
   const uint32_t *ts = tile_start + (int64_t)grp * a.Tg;
-  for (int t = tid; t < a.Tg; t += kBlock) cur[t] = ts[t] + hp[t];
-  __syncthreads();
   const int zl = grp * a.layers, zh = min(zl + a.layers, a.TZ) - 1;
   const int64_t g0 = (int64_t)c * kBlock * a.cpt;
-  for (int k = 0; k < a.cpt; ++k) {
-    int64_t g = g0 + (int64_t)k * kBlock + tid;
-    if (g >= a.M) break;
-    Box3 b = unpack_box(rec[g]);
-    if (!box_count(b)) continue;
-    int z0 = max(b.z0, zl), z1 = min(b.z1, zh);
-    for (int tz = z0; tz <= z1; ++tz)
-      for (int ty = b.y0; ty <= b.y1; ++ty)
-        for (int tx = b.x0; tx <= b.x1; ++tx) {
-          uint32_t pos = atomicAdd(&cur[group_tile(a, grp, tx, ty, tz)], 1u);
-          if (pos < a.cap) list[pos] = (uint32_t)g;
+  for (int w0 = 0; w0 < a.Tg; w0 += Tw) {
+    const int wn = min(Tw, a.Tg - w0);
+    for (int t = tid; t < wn; t += kBlock) {
+      cur[t] = ts[w0 + t] + hp[w0 + t];
+      s_mask[t] = 0ull;
+    }
+    for (int k = 0; k < a.cpt; ++k) {
+      const int64_t gk = g0 + (int64_t)k * kBlock;
+      if (gk >= a.M) break;
+      const int64_t g = gk + tid;
+      int n = 0, bx = 0, by = 0, x0 = 0, y0 = 0, z0 = 0;
+      if (g < a.M) {
+        const Box3 b = unpack_box(rec[g]);
+        if (box_count(b)) {
+          z0 = max(b.z0, zl);
+          const int z1 = min(b.z1, zh);
+          bx = b.x1 - b.x0 + 1;
+          by = b.y1 - b.y0 + 1;
+          x0 = b.x0;
+          y0 = b.y0;
+          n = z1 >= z0 ? bx * by * (z1 - z0 + 1) : 0;
         }
+      }
+      uint32_t total;
+      const uint32_t ex = block_excl_scan((uint32_t)n, sh4, total);  // synchronizes the workgroup
+      s_off[tid] = ex;
+      if (tid == 0) s_off[kBlock] = total;
+      s_org[tid] = (uint32_t)x0 | ((uint32_t)y0 << 16);
+      s_z0[tid] = (uint32_t)z0;
+      s_dim[tid] = (uint32_t)bx | ((uint32_t)by << 16);
+      __syncthreads();
+      for (uint32_t r0 = 0; r0 < total;) {
+        const int jA = entry_owner(s_off, r0);  // first Gaussian of the round (uniform)
+        const uint32_t r1 = min(r0 + (uint32_t)kBlock, s_off[min(jA + 64, kBlock)]);
+        const uint32_t e = r0 + (uint32_t)tid;
+        int t = 0, bit = 0;
+        bool act = false;
+        uint32_t gid = 0;
+        if (e < r1) {
+          const int j = entry_owner(s_off, e);
+          const uint32_t kin = e - s_off[j];
+          const uint32_t dim = s_dim[j], org = s_org[j];
+          const uint32_t ex_ = dim & 0xffffu, ey_ = dim >> 16, plane = ex_ * ey_;
+          const uint32_t lz = kin / plane, rem = kin - lz * plane;
+          const uint32_t ly = rem / ex_, lx = rem - ly * ex_;
+          const int tx = (int)(org & 0xffffu) + (int)lx, ty = (int)(org >> 16) + (int)ly,
+                    tz = (int)s_z0[j] + (int)lz;
+          t = group_tile(a, grp, tx, ty, tz) - w0;
+          act = t >= 0 && t < wn;
+          if (act) {
+            gid = (uint32_t)(gk + j);
+            bit = j - jA;
+            atomicOr(&s_mask[t], 1ull << bit);
+          }
+        }
+        __syncthreads();
+        unsigned long long mk = 0ull;
+        if (act) {
+          mk = s_mask[t];
+          const uint32_t pos = cur[t] + (uint32_t)__popcll(mk & ((1ull << bit) - 1ull));
+          if (pos < a.cap) list[pos] = gid;
+        }
+        __syncthreads();
+        if (act && (mk >> bit) == 1ull) {  // the round's last entry of this tile
+          cur[t] += (uint32_t)__popcll(mk);
+          s_mask[t] = 0ull;
+        }
+        __syncthreads();
+        r0 = r1;
+      }
+      __syncthreads();  // the next batch restages
+    }
   }
 }
 
 void launch_vox_scatter(const VoxArgs &a, const Rec3 *rec, const uint32_t *hist,
                         const uint32_t *tile_start, uint32_t *list, unsigned long long *ctl,
                         const unsigned long long *totals, hipStream_t s) {
-  hipLaunchKernelGGL(k_vox_scatter, dim3(a.C, a.G), dim3(kBlock), a.Tg * sizeof(uint32_t), s, a,
+  hipLaunchKernelGGL(k_vox_scatter, dim3(a.C, a.G), dim3(kBlock), vox_scatter_lds(a.Tg), s, a,
                      rec, hist, tile_start, list, ctl, totals);
 }
 
@@ -610,7 +692,7 @@ __global__ __launch_bounds__(kBlock) void k_vox_chain(VoxArgs a,
                                                       float *g_mean, float *g_scale, float *g_quat,
                                                       float *g_dens, int accumulate) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (g >= a.M) return;
+  if (g >= a.M || *a.totals > a.cap) return;  // overflow: the slots are incomplete
   float gp[3] = {0.f, 0.f, 0.f}, gs[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f};
   float grho = 0.f;
   const uint32_t off = offsets[g];

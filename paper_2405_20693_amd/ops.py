@@ -59,12 +59,18 @@ class Plan:
                         int(max_vox_entries), int(max_tv_voxels))
         N.call("gs_plan_reserve", self._h, ctypes.byref(r), _stream())
 
-    def check(self):
+    def check(self, raise_overflow=True):
         """(largest projection entries, largest voxel entries) since the last
-        check; raises GsError (GS_EOVERFLOW) if a call exceeded the reservation."""
+        check; if a call exceeded the reservation, raises GsError
+        (GS_EOVERFLOW), or with raise_overflow=False returns the counts and
+        True as a third item (the record is cleared either way)."""
         a, b = ctypes.c_int64(), ctypes.c_int64()
-        N.call("gs_plan_check", self._h, ctypes.byref(a), ctypes.byref(b))
-        return a.value, b.value
+        st = N.lib().gs_plan_check(self._h, ctypes.byref(a), ctypes.byref(b))
+        if st == 3 and not raise_overflow:
+            return a.value, b.value, True
+        if st != 0:
+            raise N.GsError("gs_plan_check", st, N.lib().gs_last_error().decode(errors="replace"))
+        return (a.value, b.value) if raise_overflow else (a.value, b.value, False)
 
     def set_rectify(self, enable=True):
         """False: unrectified (3DGS-style) projection rho_hat = rho."""

@@ -308,6 +308,46 @@ def test_trainer_explicit_densify_step(ops, tr):
     trainer.close()
 
 
+def test_trainer_reservation_overflow_skips_updates_and_recovers(ops, tr):
+    """The trainer sizes its reserved tile lists from its first iteration.
+    Scaling every Gaussian up 6x afterwards needs several times the entries: the
+    iterations that overflow change no parameter (their Adam steps are
+    guarded on the plans' overflow record), the run reports GS_EOVERFLOW, and
+    the grown reservation lets the next run train."""
+    import ctypes
+    from paper_2405_20693_amd import _native as N
+    wl = _small_problem(m=1500)
+    views = ops.Views.from_scan(wl.scan)
+    measured = _dev(workloads.measured_projections(wl))
+    grid = Grid(40, 40, 40, (-1.0, -1.0, -1.0), (0.05, 0.05, 0.05))
+    trainer = tr.Trainer(*_gdev(wl.gaussians), measured, views, grid, iterations=100, tv_size=8,
+                         densify_from=10 ** 6)
+    trainer.step([0], (0, 0, 0))  # sizes the reservation
+    mean, scale, quat, dens = trainer.model()
+    big = (6.0 * scale).contiguous()
+    P, n = N.GsParams(), ctypes.c_int64()
+    N.call("gs_trainer_state", trainer._h, ctypes.byref(P), ctypes.byref(n), None)
+    tmp = N.GsParams(*[getattr(P, f) for f in N.PARAM_FIELDS])
+    tmp.scale, tmp.density = big.data_ptr(), dens.data_ptr()
+    torch.cuda.synchronize()
+    N.call("gs_params_from_activated", ctypes.byref(tmp), n.value, None)  # raw from the new scales
+    N.call("gs_params_activate", ctypes.byref(P), n.value, None)          # the trainer's copies
+    torch.cuda.synchronize()
+    before = trainer.model()
+    assert torch.allclose(before[1], big, rtol=1e-5)
+    with pytest.raises(N.GsError) as e:
+        trainer.run(3)
+    assert "GS_EOVERFLOW" in str(e.value)
+    after = trainer.model()
+    for a, b in zip(after, before):
+        assert torch.equal(a, b)  # no update from an overflowing iteration
+    losses = trainer.run(2)
+    assert np.isfinite(losses).all()
+    moved = trainer.model()
+    assert not torch.equal(moved[0], before[0])
+    trainer.close()
+
+
 def _phantom_problem(n_views=24, det=96, m=6000, seed=21):
     """Reconstruction of the C3 head phantom from its exact projections: the
     initial Gaussians follow the paper's initialisation statistics (Sec. 3.3),
