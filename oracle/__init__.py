@@ -60,8 +60,20 @@ def _load():
         lib.orc_splat2d_bwd.argtypes = [i64, i64, P, i32, i32, P, f64, i32, P, P, P, P, P]
         lib.orc_splat3d.argtypes = [i64, P, i32, i32, i32, P, f64, i32, P, P, P, P]
         lib.orc_splat3d_bwd.argtypes = [i64, P, i32, i32, i32, P, f64, i32, P, P, P, P, P]
+        lib.orc_set_threads.argtypes = [i32]
+        lib.orc_max_threads.restype = i32
         _lib = lib
     return _lib
+
+
+def set_threads(n):
+    """Threads of the oracle's C sums and of its float64 torch parts; returns
+    the previous (C threads, torch threads).  Results do not depend on it."""
+    lib = _load()
+    prev = (int(lib.orc_max_threads()), torch.get_num_threads())
+    lib.orc_set_threads(int(n))
+    torch.set_num_threads(int(n))
+    return prev
 
 
 def _ptr(a):
@@ -530,6 +542,39 @@ def image_loss(render, measured, lambda_ssim=0.25):
     total = l1 + lambda_ssim * (1.0 - s)
     (gr,) = torch.autograd.grad(total, r)
     return float(total.detach()), float(l1.detach()), float(s.detach()), gr.numpy()
+
+
+def image_loss_grad_scale(render, measured, lambda_ssim=0.25):
+    """Per-pixel magnitudes that bound the FP32 rounding of d total / d render
+    (for tolerances).  With the blurred statistics of the SSIM window at each
+    pixel q and S(q) the SSIM map, the D-SSIM part of the gradient at pixel p is
+      -lambda/N sum_q w(p - q) [D1(q) + 2 x(p) D2(q) + y(p) D3(q)],
+    D2 = dS/dsxx, D3 = dS/dsxy, D1 = dS/dmx - 2 mx D2 - my D3 (chain rule of
+    sxx = blur(x^2) - mx^2, sxy = blur(xy) - mx my).  Returns (ssim_abs, l1_abs):
+    ssim_abs(p) = lambda/N sum_q w(p - q) [A1(q) + 2|x(p)| |D2(q)| + |y(p)| |D3(q)|]
+    with A1 the sum of the absolute values of the terms of D1 (dS/dmx split in
+    its two terms), and l1_abs(p) = |sign(x(p) - y(p))| / N."""
+    x = torch.tensor(np.asarray(render, np.float32), dtype=torch.float64)
+    y = torch.tensor(np.asarray(measured, np.float32), dtype=torch.float64)
+    n_pix = x.numel()
+    w = ssim_window()[None, None]
+    conv = lambda a: torch.nn.functional.conv2d(a[:, None], w, padding=5)[:, 0]
+    mx, my = conv(x), conv(y)
+    sxx = conv(x * x) - mx * mx
+    syy = conv(y * y) - my * my
+    sxy = conv(x * y) - mx * my
+    A1, A2 = 2 * mx * my + SSIM_C1, 2 * sxy + SSIM_C2
+    B1, B2 = mx * mx + my * my + SSIM_C1, sxx + syy + SSIM_C2
+    S = A1 * A2 / (B1 * B2)
+    dmx_a, dmx_b = 2 * my * A2 / (B1 * B2), 2 * mx * S / B1
+    D2 = -S / B2
+    D3 = 2 * A1 / (B1 * B2)
+    a1 = dmx_a.abs() + dmx_b.abs() + 2 * mx.abs() * D2.abs() + my.abs() * D3.abs()
+    blur_abs = lambda a: conv(a)  # the window is non-negative
+    ssim_abs = lambda_ssim / n_pix * (blur_abs(a1) + 2 * x.abs() * blur_abs(D2.abs()) +
+                                      y.abs() * blur_abs(D3.abs()))
+    l1_abs = (x - y).sign().abs() / n_pix
+    return ssim_abs.numpy(), l1_abs.numpy()
 
 
 def tv(vol):

@@ -27,6 +27,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
 
 #define AMB_REL 1e-3
 
@@ -269,3 +270,8 @@ void orc_splat3d_bwd(int64_t n, const double *rec, int32_t nx, int32_t ny, int32
     for (int c = 0; c < 10; ++c) { o[c] = acc[c]; if (ao) ao[c] = aacc[c]; if (mo) mo[c] = macc[c]; }
   }
 }
+
+/* Number of OpenMP threads of the sums above (for timing the oracle at a
+ * given thread count; results do not depend on it). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }

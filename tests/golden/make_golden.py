@@ -2,8 +2,9 @@
 
 c3_pairs.json: the exact number of in-cutoff (view, pixel, Gaussian) terms of
 the 200k-Gaussian, 75-view, 512^2 cone-beam training workload (the algorithmic
-work unit of the rasterizer's forward and backward), with a fingerprint of the
-generated inputs so that a stale file is detected.
+work unit of the rasterizer's forward and backward), the same count of
+(voxel, Gaussian) terms for the 64^3 TV blocks of its first 64 iterations, and
+a fingerprint of the generated inputs so that a stale file is detected.
 
 Run from the repository root:  python tests/golden/make_golden.py
 """
@@ -40,8 +41,16 @@ def main():
         r = oracle.project(wl.gaussians, views[v0:v0 + 15], wl.cutoff)
         per_view += [int(x) for x in r["npairs"]]
         print(v0, sum(per_view), flush=True)
+    # in-cutoff (voxel, Gaussian) terms of the 64^3 TV blocks of the first
+    # 64 iterations (the block offset is drawn with seed = iteration)
+    tv_pairs = []
+    for i in range(64):
+        tv_pairs.append(int(oracle.voxelize(wl.gaussians, workloads.tv_block_grid(wl, i),
+                                            wl.cutoff)["npairs"]))
+    print("tv blocks", sum(tv_pairs) / len(tv_pairs), flush=True)
     out = {"workload": wl.name, "fingerprint": fingerprint(wl), "cutoff": wl.cutoff,
-           "proj_pairs_per_view": per_view, "proj_pairs": int(sum(per_view))}
+           "proj_pairs_per_view": per_view, "proj_pairs": int(sum(per_view)),
+           "tv_block_pairs": tv_pairs}
     with open(os.path.join(ROOT, "tests", "golden", "c3_pairs.json"), "w") as f:
         json.dump(out, f, indent=1)
     print(out["proj_pairs"])

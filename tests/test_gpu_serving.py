@@ -7,6 +7,7 @@ import torch
 import oracle
 from oracle import parity
 from tests import scenes
+import workloads
 from workloads import Grid
 
 pytestmark = pytest.mark.gpu
@@ -88,3 +89,63 @@ def test_admission_refuses_work_above_the_budget(ops):
     from paper_2405_20693_amd._native import GsError
     with pytest.raises(GsError, match="GS_ENOMEM"):
         srv.run([small, big, small], time_scale=0.0)
+
+
+def test_serving_a_c4_sized_model(ops):
+    """A resident model of the serving workload's size class (220k phantom
+    Gaussians) next to two small ones: 512^2 and 256^2 cone projections of 1-8
+    views and a 128^3 sub-volume of the 256^3 grid, served in one mixed,
+    batched run.  Each result equals the same request run alone (within the
+    FP32 summation-order tolerance: a batch splits tile lists differently),
+    and sampled parts match the oracle: one 512^2 view, and a 24^3 block of
+    the sub-volume."""
+    big = workloads.phantom_model(1003, 220_000)
+    models = [big, scenes.random_scene(84, 1200, lo=0.02, hi=0.1),
+              scenes.random_scene(85, 800, lo=0.03, hi=0.12)]
+    dm = [_dev(m) for m in models]
+    srv = ops.Server(n_workers=3, batching=True, max_batch_views=64, hbm_budget_bytes=8 << 30)
+    for m in dm:
+        srv.add_model(*m)
+    rng = np.random.default_rng(5)
+    reqs = []
+    for i in range(10):
+        model = 0 if i % 2 == 0 else int(rng.integers(1, 3))
+        if i == 4:
+            off = (40, 96, 64)
+            h = 2.0 / 256
+            g = Grid(128, 128, 128, tuple(-1.0 + o * h for o in off), (h, h, h))
+            reqs.append({"kind": "volume", "model": 0, "arrival_s": 0.0, "grid_np": g,
+                         "grid": ops.grid_from(g),
+                         "out": torch.full((128, 128, 128), float("nan"), device="cuda")})
+            continue
+        nv = int(rng.integers(1, 9))
+        det, pitch = (512, 0.75) if i % 4 == 0 else (256, 1.5)
+        scan = workloads.cone_scan(nv, det, det, pitch)
+        scan.thetas = rng.uniform(0, 2 * np.pi) + scan.thetas
+        reqs.append({"kind": "project", "model": model, "arrival_s": 0.0, "scan": scan,
+                     "views": ops.Views.from_scan(scan),
+                     "out": torch.full((nv, det, det), float("nan"), device="cuda")})
+    res, wall = srv.run(reqs, time_scale=0.0)
+    torch.cuda.synchronize()
+    assert all(r["status"] == 0 for r in res)
+    for r in reqs:
+        m = dm[r["model"]]
+        if r["kind"] == "project":
+            alone = ops.project_forward(*m, r["views"], 3.0, ops.Plan())
+        else:
+            alone = ops.voxelize_forward(*m, r["grid"], 3.0, ops.Plan())
+        torch.cuda.synchronize()
+        a, b = alone.cpu().numpy(), r["out"].cpu().numpy()
+        assert np.all(np.isfinite(b))
+        assert np.abs(a - b).max() <= 1e-5 * max(float(np.abs(a).max()), 1e-30)
+    r = next(x for x in reqs if x["kind"] == "project" and x["model"] == 0 and x["scan"].width == 512)
+    ov = oracle.views_from_scan(r["scan"])[:1]
+    v, _ = parity.forward_violation(r["out"].cpu().numpy()[:1], oracle.project(big, ov))
+    print(f"c4-sized model, 512^2 view: worst tolerance ratio {v:.3g}", flush=True)
+    assert v <= 1.0
+    r = next(x for x in reqs if x["kind"] == "volume")
+    sg = workloads.sub_grid(r["grid_np"], 50, 60, 70, 24, 24, 24)
+    part = r["out"].cpu().numpy()[70:94, 60:84, 50:74]
+    v, _ = parity.forward_violation(part, oracle.voxelize(big, sg))
+    print(f"c4-sized model, 24^3 of the 128^3 query: worst tolerance ratio {v:.3g}", flush=True)
+    assert v <= 1.0

@@ -348,6 +348,65 @@ def test_voxel_gradient_matches_finite_differences(monkeypatch):
             assert abs(gr[key][idx] - fd) <= 1e-6 * max(1.0, abs(fd)), (key, idx)
 
 
+def _clean_gaussians(gr, n):
+    """Gaussians none of whose pairs lies within the cutoff's ambiguity band
+    (|q - kappa^2| <= 1e-3 kappa^2): a central-difference step cannot move one
+    of their terms across the cutoff."""
+    return [i for i in range(n) if all(np.all(np.asarray(gr["amb"][k])[i] == 0.0)
+                                       for k in ("mean", "scale", "quat", "density"))]
+
+
+@pytest.mark.parametrize("beam", ["cone", "parallel"])
+def test_projection_gradient_with_cutoff_matches_finite_differences(beam, monkeypatch):
+    """The cutoff branch (kappa = 3) of the analytic projection gradient: the
+    terms inside the cutoff, differentiated with the indicator held fixed,
+    equal FP64 central differences of the cutoff sum for every Gaussian whose
+    pairs all stay clear of the cutoff (its derivative is zero almost
+    everywhere)."""
+    monkeypatch.setattr(oracle, "_params",
+                        lambda g, requires_grad=False: [torch.tensor(np.asarray(a, np.float64),
+                                                                     requires_grad=requires_grad)
+                                                        for a in (g.mean, g.scale, g.quat, g.density)])
+    g = scenes.random_scene(25, 10, lo=0.04, hi=0.12, box=0.3)
+    if beam == "cone":
+        views = [oracle.cone_view(t, 4.0, 6.0, 28, 28, 0.07) for t in (0.3, 2.2)]
+    else:
+        views = [oracle.parallel_view(Rotation.random(random_state=s).as_matrix(), 28, 28, 0.05)
+                 for s in (3, 4)]
+    G = np.random.default_rng(7).standard_normal((2, 28, 28))
+    gr = oracle.project_grad(g, views, G, cutoff=3.0, with_scale=True)
+    clean = _clean_gaussians(gr, g.n)
+    assert len(clean) >= 3, clean
+    f = lambda a: float((oracle.project(_G64(a), views, cutoff=3.0)["image"] * G).sum())
+    for i in clean:
+        for key, width in (("mean", 3), ("scale", 3), ("quat", 4), ("density", None)):
+            for idx in ([(i,)] if width is None else [(i, c) for c in range(width)]):
+                fd = _fd(f, g, key, idx, 1e-6)
+                assert abs(gr[key][idx] - fd) <= 1e-6 * max(1.0, abs(fd)), (key, idx, gr[key][idx], fd)
+
+
+def test_voxel_gradient_with_cutoff_matches_finite_differences(monkeypatch):
+    """The cutoff branch (kappa = 3) of the analytic voxelizer gradient against
+    FP64 central differences, for the Gaussians whose voxel pairs all stay
+    clear of the cutoff."""
+    monkeypatch.setattr(oracle, "_params",
+                        lambda g, requires_grad=False: [torch.tensor(np.asarray(a, np.float64),
+                                                                     requires_grad=requires_grad)
+                                                        for a in (g.mean, g.scale, g.quat, g.density)])
+    g = scenes.random_scene(26, 8, lo=0.06, hi=0.15, box=0.3)
+    grd = scenes.grid(12)
+    H = np.random.default_rng(8).standard_normal((12, 12, 12))
+    gr = oracle.voxelize_grad(g, grd, H, cutoff=3.0, with_scale=True)
+    clean = _clean_gaussians(gr, g.n)
+    assert len(clean) >= 2, clean
+    f = lambda a: float((oracle.voxelize(_G64(a), grd, cutoff=3.0)["volume"] * H).sum())
+    for i in clean:
+        for key, width in (("mean", 3), ("scale", 3), ("quat", 4), ("density", None)):
+            for idx in ([(i,)] if width is None else [(i, c) for c in range(width)]):
+                fd = _fd(f, g, key, idx, 1e-6)
+                assert abs(gr[key][idx] - fd) <= 1e-6 * max(1.0, abs(fd)), (key, idx, gr[key][idx], fd)
+
+
 def test_gradient_scale_bounds_gradient():
     g = scenes.random_scene(23, 6)
     views = [oracle.cone_view(0.5, 13.64, 20.46, 32, 32, 0.05)]
@@ -370,6 +429,33 @@ def test_gradient_select_subset():
 
 
 # ----------------------------------------------------------- losses (P12) ---
+
+def test_image_loss_grad_scale_bounds_the_gradient():
+    """The per-pixel magnitudes behind the image-loss gradient tolerance: the
+    gradient's L1 and D-SSIM parts never exceed them (they are sums of the
+    absolute values of the parts' terms), an FP32 evaluation of the loss
+    gradient passes the tolerance, and a 1% error in the D-SSIM part fails it."""
+    from oracle import parity
+    rng = np.random.default_rng(31)
+    x = rng.uniform(0, 1, (2, 40, 33)).astype(np.float32)
+    y = np.clip(x + rng.normal(0, 0.2, x.shape), 0, None).astype(np.float32)
+    _, _, _, g = oracle.image_loss(x, y, 0.25)
+    ssim_abs, l1_abs = oracle.image_loss_grad_scale(x, y, 0.25)
+    l1_part = np.sign(x.astype(np.float64) - y) / x.size
+    assert np.all(np.abs(l1_part) <= l1_abs * (1 + 1e-12))
+    assert np.all(np.abs(g - l1_part) <= ssim_abs * (1 + 1e-9) + 1e-300)
+    xr = torch.tensor(x, requires_grad=True)
+    ym = torch.tensor(y)
+    w = oracle.ssim_window().float()[None, None]
+    conv = lambda a: torch.nn.functional.conv2d(a[:, None], w, padding=5)[:, 0]
+    mx, my = conv(xr), conv(ym)
+    sxx, syy, sxy = conv(xr * xr) - mx * mx, conv(ym * ym) - my * my, conv(xr * ym) - mx * my
+    S = ((2 * mx * my + 1e-4) * (2 * sxy + 9e-4)) / ((mx * mx + my * my + 1e-4) * (sxx + syy + 9e-4))
+    (g32,) = torch.autograd.grad((xr - ym).abs().mean() + 0.25 * (1 - S.mean()), xr)
+    assert parity.loss_grad_violation(g32.numpy(), g, (ssim_abs, l1_abs)) <= 1.0
+    bad = l1_part + 1.01 * (g - l1_part)
+    assert parity.loss_grad_violation(bad, g, (ssim_abs, l1_abs)) > 1.0
+
 
 def _ssim_scipy(x, y):
     from scipy.ndimage import gaussian_filter
