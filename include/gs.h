@@ -147,6 +147,9 @@ typedef struct {
   int32_t nx, ny, nz;        /* largest voxel grid (0: no voxelization part) */
   int64_t max_vox_entries;   /* (8^3 tile, Gaussian) tile-list entries per call */
   int64_t max_tv_voxels;     /* voxels of the gs_loss_tv blocks (0: none) */
+  int64_t max_records;       /* (view, Gaussian) pairs per projection call, summed over the
+                                views (0: max_views x max_gaussians) */
+  int32_t forward_only;      /* 1: no backward workspace; backward calls on the plan fail */
 } gs_reserve;               /* gs_loss_image: stacks up to max_views x height x width */
 
 /* Allocate the plan's whole workspace for problems up to r (synchronizes
@@ -164,6 +167,11 @@ typedef struct {
  * gs_plan_check (which synchronize), until gs_plan_check clears it.  Calls
  * queued before the device set it still run. */
 GS_API gs_status gs_plan_reserve(gs_plan *plan, const gs_reserve *r, hipStream_t stream);
+
+/* (host) Device bytes that gs_plan_reserve(r) allocates (its workspace, the
+ * control words included), without allocating: for sizing reservations
+ * against a memory budget. */
+GS_API gs_status gs_plan_reserve_bytes(const gs_reserve *r, int64_t *bytes);
 
 /* For a reserved plan: synchronize its last stream, report the largest
  * projection and voxel entry counts any call needed since the previous check
@@ -190,6 +198,19 @@ GS_API gs_status gs_view_cone(double theta, float src_obj, float src_det, int32_
  * At most 2^28 - 1 Gaussians per projection call (GS_EUNSUPPORTED beyond). */
 GS_API gs_status gs_project_fwd(const gs_gaussians *g, const gs_view *views, int32_t n_views,
                          float cutoff, float *image, gs_plan *plan, hipStream_t stream);
+
+/* gs_project_fwd over several Gaussian sets in one launch: view v renders
+ * models[view_model[v]] (host arrays: models [n_models], view_model
+ * [n_views]), so requests for different resident models share the binning
+ * and render launches.  Each view's image equals what gs_project_fwd gives
+ * for that model and view up to the FP32 order of partial sums (a long tile
+ * list may be split over workgroups differently).  The binning is not kept
+ * for gs_project_bwd.  plan, stream and errors as for gs_project_fwd; at most
+ * 2^28 - 1 Gaussians per model. */
+GS_API gs_status gs_project_fwd_multi(const gs_gaussians *models, int32_t n_models,
+                                      const int32_t *view_model, const gs_view *views,
+                                      int32_t n_views, float cutoff, float *image, gs_plan *plan,
+                                      hipStream_t stream);
 
 /* Gradient of L = sum(grad_image * image) with respect to the Gaussian
  * parameters (the cutoff indicator is treated as locally constant).

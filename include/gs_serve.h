@@ -1,17 +1,31 @@
 /*
  * gs_serve.h - request loop serving projection renders (Eq. 7) and volume
- * queries (Eq. 4) for many resident Gaussian models on one GPU.
+ * queries (Eq. 4, Sec. 3.2.2) for many resident Gaussian models on one GPU.
  *
- * A server owns worker threads, each with its own HIP stream and gs_plan, so
- * that requests admitted together overlap on the device.  With batching on,
- * a worker that takes a projection request also takes the queued projection
- * requests of the same model with the same detector size (up to
- * max_batch_views views) and renders all their views in one launch; results
- * are then copied to each request's output.  Admission: a request (or batch)
- * starts only while the estimated device memory of the work in flight stays
- * within hbm_budget_bytes; a request that alone exceeds it fails with
- * GS_ENOMEM in its status.  Results do not depend on which requests share a
- * batch beyond FP32 summation order.
+ * A server owns worker threads, each with its own HIP stream and gs_plan.
+ *
+ * Continuous batching (batching = 1).  When a run starts, the server measures
+ * the tile-list entries of one view of every (model, detector size) and of
+ * one volume query of every (model, grid shape) in the trace, and reserves
+ * each worker's plan (forward only) and two output slots within its share of
+ * hbm_budget_bytes: batches of up to max_batch_views views of the largest
+ * model, and the largest volume query, or fewer views per batch if that does
+ * not fit.  A worker takes the oldest queued request and, for a projection,
+ * every other queued projection with the same detector size, of any model,
+ * while the batch stays within the reservation; all their views render in one
+ * launch (gs_project_fwd_multi).  It enqueues the batch and goes back to the
+ * queue without waiting: up to two batches per worker are on the device
+ * while newly arrived requests are admitted.  Nothing is allocated and no
+ * stream is synchronized per batch, and the device memory in use stays within
+ * the budget.  A request that cannot fit its worker's reservation alone fails
+ * with GS_ENOMEM in its status; a batch whose tile lists overflow the
+ * reservation (the entry estimate was short) is served again request by
+ * request.  A request's result equals the same request run alone up to the
+ * FP32 order of partial sums (a batch may split tile lists differently).
+ *
+ * Per request (batching = 0): the plain path, one request per launch on an
+ * allocating plan, waited for, with admission while the estimated memory of
+ * the work in flight stays within hbm_budget_bytes.
  *
  * All pointers to Gaussians and outputs are device pointers owned by the
  * caller; they must stay valid until gs_server_run returns.  One
@@ -30,10 +44,11 @@ typedef struct gs_server gs_server;
 
 typedef struct {
   int32_t n_workers;         /* >= 1 (threads, each with a stream and a plan) */
-  int32_t batching;          /* 0: one request per launch; 1: merge same-model projections */
+  int32_t batching;          /* 0: plain, one request per launch; 1: continuous batching */
   int32_t max_batch_views;   /* >= 1, views per merged projection launch */
   float cutoff;              /* Mahalanobis cutoff of every request (> 0, INFINITY = none) */
-  int64_t hbm_budget_bytes;  /* > 0: estimated device memory allowed in flight */
+  int64_t hbm_budget_bytes;  /* > 0: device memory of the workers' workspaces (continuous)
+                                or of the work in flight (plain) */
 } gs_server_config;
 
 typedef enum { GS_REQ_PROJECT = 0, GS_REQ_VOLUME = 1 } gs_request_kind;
@@ -74,6 +89,10 @@ GS_API gs_status gs_server_add_model(gs_server *srv, const gs_gaussians *g, int3
  * status, if any, after all requests have finished. */
 GS_API gs_status gs_server_run(gs_server *srv, const gs_request *reqs, int64_t n, double time_scale,
                                gs_request_result *results, double *wall_s);
+
+/* Device bytes the workers reserved for the last continuous run (0 for the
+ * plain path or before a run). */
+GS_API gs_status gs_server_reserved_bytes(const gs_server *srv, int64_t *bytes);
 
 #ifdef __cplusplus
 }

@@ -60,7 +60,7 @@ class GsReserve(ctypes.Structure):
     _fields_ = [("max_gaussians", c_int64), ("max_views", c_int32), ("width", c_int32),
                 ("height", c_int32), ("max_proj_entries", c_int64), ("nx", c_int32),
                 ("ny", c_int32), ("nz", c_int32), ("max_vox_entries", c_int64),
-                ("max_tv_voxels", c_int64)]
+                ("max_tv_voxels", c_int64), ("max_records", c_int64), ("forward_only", c_int32)]
 
 
 class GsGradStats(ctypes.Structure):
@@ -113,6 +113,9 @@ EXPORTS = {
                                     ctypes.POINTER(GsView)]),
     "gs_project_fwd": (ctypes.c_int, [ctypes.POINTER(GsGaussians), ctypes.POINTER(GsView), c_int32,
                                       c_float, c_void_p, c_void_p, c_void_p]),
+    "gs_project_fwd_multi": (ctypes.c_int, [ctypes.POINTER(GsGaussians), c_int32,
+                                            ctypes.POINTER(c_int32), ctypes.POINTER(GsView), c_int32,
+                                            c_float, c_void_p, c_void_p, c_void_p]),
     "gs_project_bwd": (ctypes.c_int, [ctypes.POINTER(GsGaussians), ctypes.POINTER(GsView), c_int32,
                                       c_float, c_void_p, ctypes.POINTER(GsGrads), c_int32, c_void_p,
                                       c_void_p]),
@@ -129,6 +132,7 @@ EXPORTS = {
                                   c_int32, c_void_p, c_void_p]),
     "gs_plan_set_timing": (ctypes.c_int, [c_void_p, c_int32]),
     "gs_plan_reserve": (ctypes.c_int, [c_void_p, ctypes.POINTER(GsReserve), c_void_p]),
+    "gs_plan_reserve_bytes": (ctypes.c_int, [ctypes.POINTER(GsReserve), ctypes.POINTER(c_int64)]),
     "gs_plan_check": (ctypes.c_int, [c_void_p, ctypes.POINTER(c_int64), ctypes.POINTER(c_int64)]),
     "gs_plan_set_rectify": (ctypes.c_int, [c_void_p, c_int32]),
     "gs_project_mean_mu": (ctypes.c_int, [ctypes.POINTER(GsGaussians), ctypes.POINTER(GsView),
@@ -136,10 +140,12 @@ EXPORTS = {
     "gs_plan_stage_times": (ctypes.c_int, [c_void_p, ctypes.POINTER(c_double),
                                            ctypes.POINTER(c_int64), c_int32]),
     "gs_last_error": (ctypes.c_char_p, []),
+    "gs_probe_alu": (ctypes.c_int, [ctypes.POINTER(c_double), ctypes.POINTER(c_double), c_void_p]),
     "gs_server_create": (ctypes.c_int, [ctypes.POINTER(GsServerConfig), ctypes.POINTER(c_void_p)]),
     "gs_server_destroy": (None, [c_void_p]),
     "gs_server_add_model": (ctypes.c_int, [c_void_p, ctypes.POINTER(GsGaussians),
                                            ctypes.POINTER(c_int32)]),
+    "gs_server_reserved_bytes": (ctypes.c_int, [c_void_p, ctypes.POINTER(c_int64)]),
     "gs_server_run": (ctypes.c_int, [c_void_p, ctypes.POINTER(GsRequest), c_int64, c_double,
                                      ctypes.POINTER(GsRequestResult), ctypes.POINTER(c_double)]),
     # gs_train.h

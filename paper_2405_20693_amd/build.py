@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = ["api.hip", "project.hip", "voxel.hip", "scan_loss.hip", "serve.hip", "train.hip",
-           "trainer.hip"]
+           "trainer.hip", "probe.hip"]
 LIB = os.path.join(HERE, "libgs.so")
 
 FLAGS = [

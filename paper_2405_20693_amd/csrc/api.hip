@@ -75,6 +75,7 @@ struct gs_plan {
   bool stage_pending[kStageRing] = {};
   int stage_next = 0;
   std::vector<gs_view> up_views;     // the views p_views holds
+  std::vector<ViewSet> up_sets;      // and their Gaussian sets (multi-model calls; else empty)
   bool up_valid = false;
   unsigned long long *readback = nullptr;  // pinned, 4 entries
   // reserved mode: no allocation and no synchronization in the operator calls
@@ -159,8 +160,9 @@ void release(gs_plan *pl, Buf &b) {
 }
 
 // Grow-only workspace buffer.  Growing synchronizes `s` first so that no
-// queued kernel still uses the old buffer.
-gs_status ensure(gs_plan *pl, Buf &b, size_t bytes, hipStream_t s) {
+// queued kernel still uses the old buffer.  A buffer grows by a quarter more
+// than asked, unless `exact` (reservations).
+gs_status ensure(gs_plan *pl, Buf &b, size_t bytes, hipStream_t s, bool exact = false) {
   if (bytes == 0) bytes = 256;
   if (b.cap >= bytes) return GS_OK;
   if (pl->reserved) return fail(GS_EINVAL, "the call exceeds the plan's reservation");
@@ -169,7 +171,7 @@ gs_status ensure(gs_plan *pl, Buf &b, size_t bytes, hipStream_t s) {
     if (st != GS_OK) return st;
     release(pl, b);
   }
-  size_t want = bytes + bytes / 4;
+  size_t want = exact ? bytes : bytes + bytes / 4;
   want = (want + 255) & ~(size_t)255;
   void *p = nullptr;
   if (pl->alloc) {
@@ -290,14 +292,21 @@ void cutoff_consts(float cutoff, float &kappa, float &thr, float &qmax) {
   }
 }
 
-// Uploads per-view constants through the pinned staging ring, unless p_views
-// already holds exactly these views.
-gs_status upload_views(gs_plan *pl, const gs_view *views, int32_t nv, hipStream_t s) {
-  size_t bytes = sizeof(DevView) * (size_t)nv;
+// Uploads per-view constants (and, for a multi-model call, the views'
+// Gaussian sets after them) through the pinned staging ring, unless p_views
+// already holds exactly these.
+gs_status upload_views(gs_plan *pl, const gs_view *views, int32_t nv, hipStream_t s,
+                       const ViewSet *sets = nullptr) {
+  const size_t vbytes = sizeof(DevView) * (size_t)nv;
+  const size_t bytes = vbytes + (sets ? sizeof(ViewSet) * (size_t)nv : 0);
   void *before = pl->p_views.p;
   GS_TRY(ensure(pl, pl->p_views, bytes, s));
   if (pl->p_views.p != before) pl->up_valid = false;
-  if (pl->up_valid && pl->up_views.size() == (size_t)nv &&
+  const bool same_sets =
+      sets ? (pl->up_sets.size() == (size_t)nv &&
+              std::memcmp(pl->up_sets.data(), sets, sizeof(ViewSet) * (size_t)nv) == 0)
+           : pl->up_sets.empty();
+  if (pl->up_valid && same_sets && pl->up_views.size() == (size_t)nv &&
       std::memcmp(pl->up_views.data(), views, sizeof(gs_view) * (size_t)nv) == 0)
     return GS_OK;
   const int k = pl->stage_next;
@@ -318,12 +327,18 @@ gs_status upload_views(gs_plan *pl, const gs_view *views, int32_t nv, hipStream_
   }
   DevView *dv = reinterpret_cast<DevView *>(pl->stage[k]);
   for (int i = 0; i < nv; ++i) dv[i] = make_dev_view(views[i]);
+  if (sets)
+    std::memcpy(static_cast<char *>(pl->stage[k]) + vbytes, sets, sizeof(ViewSet) * (size_t)nv);
   pl->up_valid = false;
   if (hipMemcpyAsync(pl->p_views.p, pl->stage[k], bytes, hipMemcpyHostToDevice, s) != hipSuccess)
     return fail(GS_EHIP, "view upload failed");
   if (hipEventRecord(pl->stage_done[k], s) != hipSuccess) return fail(GS_EHIP, "hipEventRecord");
   pl->stage_pending[k] = true;
   pl->up_views.assign(views, views + nv);
+  if (sets)
+    pl->up_sets.assign(sets, sets + nv);
+  else
+    pl->up_sets.clear();
   pl->up_valid = true;
   return GS_OK;
 }
@@ -346,13 +361,30 @@ bool same_vox(const gs_plan *pl, const gs_gaussians *g, const gs_grid *grid, flo
 }
 
 // Projection + binning: records, tile lists and backward slot offsets.
+// models/view_model: NULL for a single-model call on g; else view v renders
+// models[view_model[v]] (g is then models[view_model[0]]).
 gs_status proj_bin(gs_plan *pl, const gs_gaussians *g, const gs_view *views, int32_t nv,
-                   float cutoff, hipStream_t s) {
+                   float cutoff, hipStream_t s, const gs_gaussians *models = nullptr,
+                   const int32_t *view_model = nullptr) {
   pl->p_valid = false;
   ProjArgs a{};
   a.mean = g->mean; a.scale = g->scale; a.quat = g->quat; a.dens = g->density;
   a.M = g->n;
   a.V = nv;
+  std::vector<ViewSet> sets;
+  if (models) {
+    sets.resize((size_t)nv);
+    int64_t r = 0;
+    for (int v = 0; v < nv; ++v) {
+      const gs_gaussians &m = models[view_model[v]];
+      sets[(size_t)v] = ViewSet{m.mean, m.scale, m.quat, m.density, m.n, r};
+      r += m.n;
+      a.M = std::max<int64_t>(a.M, m.n);
+    }
+    a.R = r;
+  } else {
+    a.R = (int64_t)nv * a.M;
+  }
   a.width = views[0].width;
   a.height = views[0].height;
   a.TX = (a.width + kTile - 1) / kTile;
@@ -376,11 +408,12 @@ gs_status proj_bin(gs_plan *pl, const gs_gaussians *g, const gs_view *views, int
   cutoff_consts(cutoff, a.kappa, a.thr, a.qmax);
   a.rectify = pl->rectify;
   a.ovf_host = pl->reserved ? pl->ovf_flag_dev : nullptr;
-  const int64_t VM = (int64_t)nv * a.M, VT = (int64_t)nv * a.T, VC = (int64_t)nv * a.C;
+  const int64_t VM = a.R, VT = (int64_t)nv * a.T, VC = (int64_t)nv * a.C;
   if (VT + 1 > 0x7fffffffLL || VC + 1 > 0x7fffffffLL)
     return fail(GS_EUNSUPPORTED, "too many views in one call");
-  GS_TRY(upload_views(pl, views, nv, s));
+  GS_TRY(upload_views(pl, views, nv, s, models ? sets.data() : nullptr));
   a.views = P<DevView>(pl->p_views);
+  a.sets = models ? reinterpret_cast<const ViewSet *>(P<DevView>(pl->p_views) + nv) : nullptr;
   GS_TRY(ensure(pl, pl->p_rec, sizeof(Rec2) * VM, s));
   GS_TRY(ensure(pl, pl->p_hist, 4 * VC * a.T, s));
   GS_TRY(ensure(pl, pl->p_tile_total, 4 * VT, s));
@@ -414,7 +447,9 @@ gs_status proj_bin(gs_plan *pl, const gs_gaussians *g, const gs_view *views, int
   unsigned long long entries;
   if (pl->reserved) {
     // no readback: the scatter keeps what the reserved list and slots hold
-    entries = std::min(pl->p_list.cap / 8, pl->p_slots.cap >= 16 ? (pl->p_slots.cap - 16) / 24 : 0);
+    entries = pl->p_list.cap / 8;
+    if (!pl->res.forward_only)
+      entries = std::min<unsigned long long>(entries, pl->p_slots.cap >= 16 ? (pl->p_slots.cap - 16) / 24 : 0);
     entries = std::min<unsigned long long>(entries, 0xffffffffull);
   } else {
     if (hipMemcpyAsync(pl->readback, pl->p_totals.p, 16, hipMemcpyDeviceToHost, s) != hipSuccess)
@@ -448,7 +483,7 @@ gs_status proj_bin(gs_plan *pl, const gs_gaussians *g, const gs_view *views, int
   pl->pkey.mean = g->mean; pl->pkey.scale = g->scale; pl->pkey.quat = g->quat;
   pl->pkey.dens = g->density; pl->pkey.n = g->n; pl->pkey.cutoff = cutoff;
   pl->pkey.views.assign(views, views + nv);
-  pl->p_valid = true;
+  pl->p_valid = models == nullptr;  // a multi-model binning serves no backward
   return GS_OK;
 }
 
@@ -509,7 +544,8 @@ gs_status vox_bin(gs_plan *pl, const gs_gaussians *g, const gs_grid *grid, float
   GS_TRY(check_launch("voxel binning"));
   unsigned long long entries;
   if (pl->reserved) {
-    entries = std::min(pl->v_list.cap / 4, pl->v_slots.cap / 40);
+    entries = pl->v_list.cap / 4;
+    if (!pl->res.forward_only) entries = std::min<unsigned long long>(entries, pl->v_slots.cap / 40);
     entries = std::min<unsigned long long>(entries, 0xffffffffull);
   } else {
     if (hipMemcpyAsync(pl->readback, pl->v_totals.p, 16, hipMemcpyDeviceToHost, s) != hipSuccess)
@@ -728,20 +764,27 @@ gs_status gs_plan_status(gs_plan *p, int64_t *skipped, int64_t *tile_entries) {
   return GS_OK;
 }
 
-gs_status gs_plan_reserve(gs_plan *p, const gs_reserve *r, hipStream_t s) {
-  if (!p || !r) return fail(GS_EINVAL, "plan or reservation is NULL");
+}  // extern "C"
+
+namespace {
+
+gs_status check_reserve(const gs_reserve *r) {
   if (r->max_gaussians < 0 || r->max_gaussians > 0x7fffffffLL || r->max_views < 0 ||
       r->max_proj_entries < 0 || r->max_proj_entries >= 0xffffffffLL || r->max_vox_entries < 0 ||
-      r->max_vox_entries >= 0xffffffffLL || r->max_tv_voxels < 0 ||
+      r->max_vox_entries >= 0xffffffffLL || r->max_tv_voxels < 0 || r->max_records < 0 ||
       (r->max_views > 0 && (r->width < 1 || r->height < 1 || r->width > 16384 || r->height > 16384)) ||
       (r->nx < 0 || r->ny < 0 || r->nz < 0 || r->nx > 16384 || r->ny > 16384 || r->nz > 16384))
     return fail(GS_EINVAL, "reservation sizes out of range");
-  p->reserved = false;  // allocate first
-  p->used = true;
-  p->last_stream = s;
+  return GS_OK;
+}
+
+// The workspace of a reservation: take(buffer, bytes) for every buffer, in
+// one place for allocating it and for counting its bytes; with staging, the
+// pinned host staging ring for the view constants is sized too.
+template <class Take>
+gs_status reserve_layout(gs_plan *p, const gs_reserve *r, bool staging, Take take) {
   const int64_t M = std::max<int64_t>(r->max_gaussians, 1);
   const int64_t Cmax16 = (M + 4095) / 4096;  // chunks at the largest chunk size
-  GS_TRY(ensure_skipped(p, s));
   if (r->max_views > 0) {
     const int64_t V = r->max_views;
     const int64_t T = (int64_t)((r->width + kTile - 1) / kTile) * ((r->height + kTile - 1) / kTile);
@@ -750,24 +793,27 @@ gs_status gs_plan_reserve(gs_plan *p, const gs_reserve *r, hipStream_t s) {
     // stays below max(V ceil(M / 4096), 1024 + V) for any M' <= M and V' <= V
     const int64_t VC = std::max<int64_t>(V * Cmax16, 1024 + V);
     const int64_t VT = V * T, E = r->max_proj_entries;
-    GS_TRY(ensure(p, p->p_views, sizeof(DevView) * V, s));
-    GS_TRY(ensure(p, p->p_rec, sizeof(Rec2) * V * M, s));
-    GS_TRY(ensure(p, p->p_hist, 4 * VC * T, s));
-    GS_TRY(ensure(p, p->p_tile_total, 4 * VT, s));
-    GS_TRY(ensure(p, p->p_tile_start, 4 * (VT + 1), s));
-    GS_TRY(ensure(p, p->p_chunk_cnt, 4 * VC, s));
-    GS_TRY(ensure(p, p->p_chunk_start, 4 * (VC + 1), s));
-    GS_TRY(ensure(p, p->p_offsets, 4 * (V * M + 1), s));
-    GS_TRY(ensure(p, p->p_totals, 16, s));
-    GS_TRY(ensure(p, p->p_scan_tmp, 4 * (size_t)(2 * ((VT + 4095) / 4096) + 2 * ((VC + 4095) / 4096) + 2), s));
-    GS_TRY(ensure(p, p->p_list, 8 * (size_t)std::max<int64_t>(E, 1), s));
-    GS_TRY(ensure(p, p->p_slots, 24 * (size_t)std::max<int64_t>(E, 1) + 16, s));
-    GS_TRY(ensure(p, p->p_part, 72 * (size_t)proj_chain_chunks((int)V) * (size_t)M, s));
+    const int64_t R = r->max_records > 0 ? r->max_records : V * M;
+    GS_TRY(take(p->p_views, (sizeof(DevView) + sizeof(ViewSet)) * V));
+    GS_TRY(take(p->p_rec, sizeof(Rec2) * R));
+    GS_TRY(take(p->p_hist, 4 * VC * T));
+    GS_TRY(take(p->p_tile_total, 4 * VT));
+    GS_TRY(take(p->p_tile_start, 4 * (VT + 1)));
+    GS_TRY(take(p->p_chunk_cnt, 4 * VC));
+    GS_TRY(take(p->p_chunk_start, 4 * (VC + 1)));
+    GS_TRY(take(p->p_offsets, 4 * (R + 1)));
+    GS_TRY(take(p->p_totals, 16));
+    GS_TRY(take(p->p_scan_tmp, 4 * (size_t)(2 * ((VT + 4095) / 4096) + 2 * ((VC + 4095) / 4096) + 2)));
+    GS_TRY(take(p->p_list, 8 * (size_t)std::max<int64_t>(E, 1)));
+    if (!r->forward_only) {
+      GS_TRY(take(p->p_slots, 24 * (size_t)std::max<int64_t>(E, 1) + 16));
+      GS_TRY(take(p->p_part, 72 * (size_t)proj_chain_chunks((int)V) * (size_t)M));
+    }
     // render parts x tiles stays below 8192 + tiles
-    GS_TRY(ensure(p, p->p_fpart, 4 * (size_t)kBlock * (size_t)(8192 + VT), s));
-    GS_TRY(ensure(p, p->l_part, 8 * (size_t)ssim_num_blocks((int)V, r->height, r->width), s));
-    for (int k = 0; k < gs_plan::kStageRing; ++k) {
-      const size_t bytes = sizeof(DevView) * (size_t)V;
+    GS_TRY(take(p->p_fpart, 4 * (size_t)kBlock * (size_t)(8192 + VT)));
+    GS_TRY(take(p->l_part, 8 * (size_t)ssim_num_blocks((int)V, r->height, r->width)));
+    for (int k = 0; staging && k < gs_plan::kStageRing; ++k) {
+      const size_t bytes = (sizeof(DevView) + sizeof(ViewSet)) * (size_t)V;
       if (p->stage_cap[k] < bytes) {
         if (p->stage_pending[k] && hipEventSynchronize(p->stage_done[k]) != hipSuccess)
           return fail(GS_EHIP, "hipEventSynchronize");
@@ -791,25 +837,62 @@ gs_status gs_plan_reserve(gs_plan *p, const gs_reserve *r, hipStream_t s) {
     const int64_t Tg = std::max<int64_t>(4096, TX * TY), GT = TX * TY * TZ + Tg, G = TZ;
     const int64_t GC = std::max<int64_t>(G * Cmax16, 1024 + G);
     const int64_t E = r->max_vox_entries, nb = (M + 4095) / 4096 + 1;
-    GS_TRY(ensure(p, p->v_rec, sizeof(Rec3) * (size_t)M, s));
-    GS_TRY(ensure(p, p->v_count, 4 * (size_t)M, s));
-    GS_TRY(ensure(p, p->v_offsets, 4 * (size_t)(M + 1), s));
-    GS_TRY(ensure(p, p->v_scan_tmp, 4 * (size_t)(2 * nb + 1), s));
-    GS_TRY(ensure(p, p->v_hist, 4 * (size_t)(GC * Tg), s));
-    GS_TRY(ensure(p, p->v_tile_total, 4 * (size_t)GT, s));
-    GS_TRY(ensure(p, p->v_tile_start, 4 * (size_t)(GT + 1), s));
-    GS_TRY(ensure(p, p->v_totals, 16, s));
-    GS_TRY(ensure(p, p->v_list, 4 * (size_t)std::max<int64_t>(E, 1), s));
-    GS_TRY(ensure(p, p->v_slots, 40 * (size_t)std::max<int64_t>(E, 1), s));
-    GS_TRY(ensure(p, p->v_fpart, 4 * 2 * (size_t)kBlock * (size_t)(4096 + GT), s));  // parts x tiles
+    GS_TRY(take(p->v_rec, sizeof(Rec3) * (size_t)M));
+    GS_TRY(take(p->v_count, 4 * (size_t)M));
+    GS_TRY(take(p->v_offsets, 4 * (size_t)(M + 1)));
+    GS_TRY(take(p->v_scan_tmp, 4 * (size_t)(2 * nb + 1)));
+    GS_TRY(take(p->v_hist, 4 * (size_t)(GC * Tg)));
+    GS_TRY(take(p->v_tile_total, 4 * (size_t)GT));
+    GS_TRY(take(p->v_tile_start, 4 * (size_t)(GT + 1)));
+    GS_TRY(take(p->v_totals, 16));
+    GS_TRY(take(p->v_list, 4 * (size_t)std::max<int64_t>(E, 1)));
+    if (!r->forward_only) GS_TRY(take(p->v_slots, 40 * (size_t)std::max<int64_t>(E, 1)));
+    GS_TRY(take(p->v_fpart, 4 * 2 * (size_t)kBlock * (size_t)(4096 + GT)));  // parts x tiles
   }
   if (r->max_tv_voxels > 0) {
     const size_t nb = (size_t)((r->max_tv_voxels + kBlock - 1) / kBlock);
-    GS_TRY(ensure(p, p->l_part, 4 * nb, s));
+    GS_TRY(take(p->l_part, 4 * nb));
   }
+  return GS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gs_status gs_plan_reserve(gs_plan *p, const gs_reserve *r, hipStream_t s) {
+  if (!p || !r) return fail(GS_EINVAL, "plan or reservation is NULL");
+  GS_TRY(check_reserve(r));
+  p->reserved = false;  // allocate first
+  p->used = true;
+  p->last_stream = s;
+  GS_TRY(ensure_skipped(p, s));
+  GS_TRY(reserve_layout(p, r, true,
+                        [&](Buf &b, size_t bytes) { return ensure(p, b, bytes, s, true); }));
   GS_TRY(sync_stream(p, s));
   p->res = *r;
   p->reserved = true;
+  return GS_OK;
+}
+
+gs_status gs_plan_reserve_bytes(const gs_reserve *r, int64_t *bytes) {
+  if (!r || !bytes) return fail(GS_EINVAL, "reservation or bytes is NULL");
+  GS_TRY(check_reserve(r));
+  gs_plan tmp;  // holds no memory: only its buffer slots are named
+  std::vector<std::pair<const Buf *, size_t>> sizes;
+  GS_TRY(reserve_layout(&tmp, r, false, [&](Buf &b, size_t n) {
+    n = (std::max<size_t>(n, 256) + 255) & ~(size_t)255;
+    for (auto &e : sizes)
+      if (e.first == &b) {
+        e.second = std::max(e.second, n);
+        return GS_OK;
+      }
+    sizes.emplace_back(&b, n);
+    return GS_OK;
+  }));
+  int64_t total = 64;  // control words
+  for (auto &e : sizes) total += (int64_t)e.second;
+  *bytes = total;
   return GS_OK;
 }
 
@@ -913,9 +996,9 @@ gs_status gs_view_cone(double theta, float src_obj, float src_det, int32_t width
   return GS_OK;
 }
 
-gs_status gs_project_fwd(const gs_gaussians *g, const gs_view *views, int32_t n_views, float cutoff,
-                         float *image, gs_plan *plan, hipStream_t stream) {
-  GS_TRY(check_gaussians(g));
+static gs_status project_fwd(const gs_gaussians *g, const gs_gaussians *models,
+                             const int32_t *view_model, const gs_view *views, int32_t n_views,
+                             float cutoff, float *image, gs_plan *plan, hipStream_t stream) {
   GS_TRY(check_views(views, n_views));
   GS_TRY(check_cutoff(cutoff));
   if (!image) return fail(GS_EINVAL, "image is NULL");
@@ -929,13 +1012,16 @@ gs_status gs_project_fwd(const gs_gaussians *g, const gs_view *views, int32_t n_
   plan->used = true;
   plan->last_stream = stream;
   const size_t pix = (size_t)n_views * views[0].width * views[0].height;
-  if (g->n == 0) {
+  int64_t most = g->n;
+  if (models)
+    for (int v = 0; v < n_views; ++v) most = std::max<int64_t>(most, models[view_model[v]].n);
+  if (most == 0) {
     plan->p_valid = false;
     if (hipMemsetAsync(image, 0, sizeof(float) * pix, stream) != hipSuccess)
       return fail(GS_EHIP, "hipMemsetAsync");
     return tp.owned ? sync_stream(plan, stream) : GS_OK;
   }
-  GS_TRY(proj_bin(plan, g, views, n_views, cutoff, stream));
+  GS_TRY(proj_bin(plan, g, views, n_views, cutoff, stream, models, view_model));
   {
     StageTimer t(plan, GS_STAGE_RENDER_FWD, stream);
     float *partial = nullptr;
@@ -951,6 +1037,29 @@ gs_status gs_project_fwd(const gs_gaussians *g, const gs_view *views, int32_t n_
   GS_TRY(check_launch("render forward"));
   if (tp.owned) GS_TRY(sync_stream(plan, stream));
   return GS_OK;
+}
+
+gs_status gs_project_fwd(const gs_gaussians *g, const gs_view *views, int32_t n_views, float cutoff,
+                         float *image, gs_plan *plan, hipStream_t stream) {
+  GS_TRY(check_gaussians(g));
+  return project_fwd(g, nullptr, nullptr, views, n_views, cutoff, image, plan, stream);
+}
+
+gs_status gs_project_fwd_multi(const gs_gaussians *models, int32_t n_models,
+                               const int32_t *view_model, const gs_view *views, int32_t n_views,
+                               float cutoff, float *image, gs_plan *plan, hipStream_t stream) {
+  if (!models || n_models < 1) return fail(GS_EINVAL, "models is NULL or n_models < 1");
+  if (!view_model) return fail(GS_EINVAL, "view_model is NULL");
+  for (int i = 0; i < n_models; ++i) {
+    gs_status st = check_gaussians(&models[i]);
+    if (st != GS_OK) return fail(st, std::string(gs_last_error()) + " (model " + std::to_string(i) + ")");
+  }
+  if (n_views < 1) return fail(GS_EINVAL, "n_views < 1");
+  for (int v = 0; v < n_views; ++v)
+    if (view_model[v] < 0 || view_model[v] >= n_models)
+      return fail(GS_EINVAL, "view_model[" + std::to_string(v) + "] out of range");
+  return project_fwd(&models[view_model[0]], models, view_model, views, n_views, cutoff, image,
+                     plan, stream);
 }
 
 static gs_status project_bwd(const gs_gaussians *g, const gs_view *views, int32_t n_views, float cutoff,
@@ -1157,6 +1266,16 @@ namespace gsk {
 
 const unsigned long long *plan_control_words(const gs_plan *p) {
   return p ? reinterpret_cast<const unsigned long long *>(p->skipped.p) : nullptr;
+}
+
+const unsigned long long *plan_entries_needed(const gs_plan *p, int voxel) {
+  if (!p) return nullptr;
+  return reinterpret_cast<const unsigned long long *>(voxel ? p->v_totals.p : p->p_totals.p);
+}
+
+int64_t plan_entry_capacity(const gs_plan *p, int voxel) {
+  if (!p || !p->reserved) return 0;
+  return (int64_t)(voxel ? p->v_list.cap / 4 : p->p_list.cap / 8);
 }
 
 gs_status adam_step_guarded(const gs_params *p, int64_t n, const gs_grads *grads,

@@ -340,9 +340,17 @@ __device__ inline int entry_owner(const uint32_t *off, uint32_t e) {
 
 // ------------------------------------------------------------ launchers --
 
+// Gaussian set of one view of a multi-model projection call (views of one
+// call may render different resident models).
+struct ViewSet {
+  const float *mean, *scale, *quat, *dens;
+  int64_t M;      // Gaussians of the set
+  int64_t rbase;  // the view's first record (and slot offset) index
+};
+
 struct ProjArgs {
   const float *mean, *scale, *quat, *dens;
-  int64_t M;
+  int64_t M;                      // Gaussians (multi-model calls: the largest set)
   int V;
   const DevView *views;
   int width, height, TX, TY, T;   // tiles per view T = TX * TY
@@ -354,7 +362,16 @@ struct ProjArgs {
   uint32_t cap;                   // tile-list entries the list and slot buffers hold
   const unsigned long long *totals;  // totals[0]: entries this call needs (> cap: overflow)
   unsigned int *ovf_host;         // host-visible overflow flag of the plan (reserved plans), or null
+  const ViewSet *sets;            // per-view Gaussian sets (multi-model forward), or null
+  int64_t R;                      // records of the call: V M, or the sum of the views' sets
 };
+
+// The Gaussian set and record base of view v (the call's one set unless the
+// call renders several models).
+__device__ inline ViewSet view_set(const ProjArgs &a, int v) {
+  if (a.sets) return a.sets[v];
+  return ViewSet{a.mean, a.scale, a.quat, a.dens, a.M, (int64_t)v * a.M};
+}
 
 void launch_mean_mu(const ProjArgs &a, float *mu_out, float *density_out, hipStream_t s);
 void launch_proj_hist(const ProjArgs &a, Rec2 *rec, uint32_t *hist, uint32_t *chunk_cnt,
@@ -456,6 +473,11 @@ int tv_num_blocks(int nx, int ny, int nz);
 void set_last_error(const char *msg);
 // A plan's device control words (layout above), or null before its first call.
 const unsigned long long *plan_control_words(const gs_plan *p);
+// Device word holding the tile-list entries the plan's last projection
+// (voxel = 0) or voxelization (voxel = 1) binning needed, or null; and the
+// entries a reserved plan holds for that operator (0 if not reserved).
+const unsigned long long *plan_entries_needed(const gs_plan *p, int voxel);
+int64_t plan_entry_capacity(const gs_plan *p, int voxel);
 // gs_adam_step that does nothing on the device when plan g0 or g1 (either may
 // be null) records a call that overflowed its reservation since its last check.
 gs_status adam_step_guarded(const gs_params *p, int64_t n, const gs_grads *grads,

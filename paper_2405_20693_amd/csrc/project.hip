@@ -51,18 +51,19 @@ __global__ __launch_bounds__(kBlock) void k_proj_hist(ProjArgs a, Rec2 *__restri
   for (int t = tid; t < a.T; t += kBlock) sh[t] = 0;
   __syncthreads();
   const DevView V = a.views[v];
+  const ViewSet S = view_set(a, v);
   uint32_t cnt = 0, skip = 0;
   const int64_t g0 = (int64_t)c * kBlock * a.cpt;
   for (int k = 0; k < a.cpt; ++k) {
     int64_t g = g0 + (int64_t)k * kBlock + tid;
-    if (g >= a.M) break;
+    if (g >= S.M) break;
     Gauss G;
-    load_gauss(a.mean, a.scale, a.quat, a.dens, g, G);
+    load_gauss(S.mean, S.scale, S.quat, S.dens, g, G);
     Proj2 P;
     project_one(G, V, P);
     Rec2 r = make_rec2(G, P, V, a);
     skip += P.ok ? 0u : 1u;
-    rec[(int64_t)v * a.M + g] = r;
+    rec[S.rbase + g] = r;
     Rect2 rc = unpack_rect(r.r0, r.r1);
     int n = rect_count(rc);
     cnt += (uint32_t)n;
@@ -232,6 +233,7 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
   const uint32_t *h = hist + ((int64_t)v * a.C + c) * a.T;
   const uint32_t *ts = tile_start + (int64_t)v * a.T;
   const int64_t g0 = (int64_t)c * kBlock * a.cpt;
+  const ViewSet S = view_set(a, v);
   uint32_t base = 0;
   for (int w0 = 0; w0 < a.T; w0 += Tw) {
     const int wn = min(Tw, a.T - w0);
@@ -242,19 +244,19 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
     base = chunk_start[v * a.C + c];
     for (int k = 0; k < a.cpt; ++k) {
       const int64_t gk = g0 + (int64_t)k * kBlock;
-      if (gk >= a.M) break;
+      if (gk >= S.M) break;
       const int64_t g = gk + tid;
-      const bool valid = g < a.M;
+      const bool valid = g < S.M;
       Rect2 rc{1, 0, 0, 0};
       Rec2 r{};
       if (valid) {
-        r = rec[(int64_t)v * a.M + g];
+        r = rec[S.rbase + g];
         rc = unpack_rect(r.r0, r.r1);
       }
       const int n = valid ? rect_count(rc) : 0;
       uint32_t total;
       const uint32_t ex = block_excl_scan((uint32_t)n, sh4, total);  // synchronizes the workgroup
-      if (valid && w0 == 0) offsets[(int64_t)v * a.M + g] = base + ex;
+      if (valid && w0 == 0) offsets[S.rbase + g] = base + ex;
       s_off[tid] = ex;
       if (tid == 0) s_off[kBlock] = total;
       s_org[tid] = (uint32_t)rc.x0 | ((uint32_t)rc.y0 << 16);
@@ -323,9 +325,9 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
       __syncthreads();  // the next batch restages
     }
   }
-  // the slot total closes the offsets array (offsets[V M]); the last chunk of
+  // the slot total closes the offsets array (offsets[R]); the last chunk of
   // the last view ends there
-  if (v == a.V - 1 && c == a.C - 1 && tid == 0) offsets[(int64_t)a.V * a.M] = base;
+  if (v == a.V - 1 && c == a.C - 1 && tid == 0) offsets[a.R] = base;
 }
 
 void launch_proj_scatter(const ProjArgs &a, const Rec2 *rec, const uint32_t *hist,
@@ -387,7 +389,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
   uint32_t beg, end;
   list_part(min(tile_start[item], a.cap), min(tile_start[item + 1], a.cap), part, a.parts, beg,
             end);
-  const Rec2 *rv = rec + (int64_t)v * a.M;
+  const Rec2 *rv = rec + (a.sets ? a.sets[v].rbase : (int64_t)v * a.M);
   const float thr = a.thr;
   float acc[kSub];
 #pragma unroll

@@ -51,12 +51,14 @@ class Plan:
         return {"skipped": sk.value, "tile_entries": en.value}
 
     def reserve(self, max_gaussians, max_views=0, width=0, height=0, max_proj_entries=0,
-                grid=(0, 0, 0), max_vox_entries=0, max_tv_voxels=0):
+                grid=(0, 0, 0), max_vox_entries=0, max_tv_voxels=0, max_records=0,
+                forward_only=False):
         """Allocate for problems up to these sizes and stop allocating and
         synchronizing in operator calls (gs_plan_reserve)."""
         r = N.GsReserve(int(max_gaussians), int(max_views), int(width), int(height),
                         int(max_proj_entries), int(grid[0]), int(grid[1]), int(grid[2]),
-                        int(max_vox_entries), int(max_tv_voxels))
+                        int(max_vox_entries), int(max_tv_voxels), int(max_records),
+                        int(bool(forward_only)))
         N.call("gs_plan_reserve", self._h, ctypes.byref(r), _stream())
 
     def check(self, raise_overflow=True):
@@ -186,6 +188,23 @@ def project_forward(mean, scale, quat, density, views: Views, cutoff=3.0, plan=N
     N.call("gs_project_fwd", ctypes.byref(g), views.arr, views.n, float(cutoff),
            _dev(out, "image", (views.n, views.height, views.width)),
            plan.handle if plan is not None else None, _stream())
+    return out
+
+
+def project_forward_multi(models, view_model, views: Views, cutoff=3.0, plan=None, out=None):
+    """Views of several Gaussian sets in one launch (gs_project_fwd_multi):
+    view v renders models[view_model[v]], each model a (mean, scale, quat,
+    density) tuple of tensors.  Returns the image stack [V, H, W]."""
+    arr = (N.GsGaussians * len(models))()
+    for i, m in enumerate(models):
+        arr[i] = _gaussians(*m)
+    vm = (ctypes.c_int32 * views.n)(*[int(x) for x in view_model])
+    dev = models[0][0].device
+    if out is None:
+        out = torch.empty((views.n, views.height, views.width), device=dev, dtype=torch.float32)
+    keep = plan if plan is not None else Plan()  # held until the call returns
+    N.call("gs_project_fwd_multi", arr, len(models), vm, views.arr, views.n, float(cutoff),
+           _dev(out, "out", (views.n, views.height, views.width)), keep.handle, _stream())
     return out
 
 
@@ -332,20 +351,27 @@ def voxelize(mean, scale, quat, density, grid, cutoff=3.0, plan=None):
 
 class Server:
     """Request loop of include/gs_serve.h: worker threads with their own
-    streams and plans, merging of same-model projection requests, admission
-    by an estimated device-memory budget.  All work runs in libgs.so."""
+    streams and plans; continuous batching of projections across models into
+    one launch within reserved workspaces sized from the HBM budget, or the
+    plain one-request-per-launch path.  All work runs in libgs.so."""
 
     def __init__(self, n_workers=4, batching=True, max_batch_views=128, cutoff=3.0,
                  hbm_budget_bytes=None):
         if hbm_budget_bytes is None:
             free, _ = torch.cuda.mem_get_info()
-            hbm_budget_bytes = int(0.5 * free)
+            hbm_budget_bytes = int(0.25 * free)
         cfg = N.GsServerConfig(int(n_workers), int(bool(batching)), int(max_batch_views),
                                float(cutoff), int(hbm_budget_bytes))
         h = ctypes.c_void_p()
         N.call("gs_server_create", ctypes.byref(cfg), ctypes.byref(h))
         self._h = h
         self._models = []
+
+    def reserved_bytes(self):
+        """Device bytes the workers reserved for the last continuous run."""
+        b = ctypes.c_int64()
+        N.call("gs_server_reserved_bytes", self._h, ctypes.byref(b))
+        return b.value
 
     def add_model(self, mean, scale, quat, density):
         g = _gaussians(mean, scale, quat, density)

@@ -119,3 +119,27 @@ def test_bindings_keep_temporary_plans_alive():
             if isinstance(node, ast.Attribute) and node.attr == "handle":
                 inner = node.value
                 assert not isinstance(inner, (ast.BoolOp, ast.Call)), f"{name}:{node.lineno}"
+
+
+def test_reserve_bytes_counts_the_workspace(native):
+    """gs_plan_reserve_bytes (host only): a tile-list entry costs 8 B of list
+    and 24 B of backward slots; forward-only plans leave out the slots and
+    chain partials; a record costs 32 B plus a 4-B slot offset."""
+    def nbytes(**kw):
+        r = native.GsReserve()
+        for k, v in kw.items():
+            setattr(r, k, v)
+        out = ctypes.c_int64()
+        native.call("gs_plan_reserve_bytes", ctypes.byref(r), ctypes.byref(out))
+        return out.value
+    base = dict(max_gaussians=100_000, max_views=8, width=512, height=512)
+    e0 = nbytes(max_proj_entries=1 << 20, **base)
+    e1 = nbytes(max_proj_entries=2 << 20, **base)
+    assert e1 - e0 == (8 + 24) << 20
+    f0 = nbytes(max_proj_entries=1 << 20, forward_only=1, **base)
+    assert e0 - f0 >= (24 << 20) + 72 * 100_000
+    r0 = nbytes(max_proj_entries=1 << 20, forward_only=1, max_records=400_000, **base)
+    r1 = nbytes(max_proj_entries=1 << 20, forward_only=1, max_records=800_000, **base)
+    assert r1 - r0 == 36 * 400_000
+    with pytest.raises(native.GsError, match="GS_EINVAL"):
+        nbytes(max_gaussians=1000, max_views=-1, width=8, height=8)

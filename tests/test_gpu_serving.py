@@ -46,6 +46,38 @@ def _requests(ops, rng, n):
     return reqs
 
 
+def test_multi_model_projection_matches_single_model_calls(ops):
+    """gs_project_fwd_multi: views of three models of different sizes (one of
+    them empty) in one launch equal each model's own gs_project_fwd of the
+    same views, within the FP32 order of partial sums, and the oracle; a
+    view index beyond the models is refused before any launch."""
+    models = [scenes.random_scene(86, 2500, lo=0.02, hi=0.1), scenes.random_scene(87, 700, lo=0.03, hi=0.12),
+              scenes.random_scene(88, 0)]
+    dm = [_dev(m) for m in models]
+    th = [0.2, 1.1, 2.5, 3.3, 4.4, 5.9, 0.7]
+    vm = [0, 1, 0, 2, 1, 1, 0]
+    views = ops.Views.cone(th, 13.64, 20.46, 56, 44, 0.045)
+    img = ops.project_forward_multi(dm, vm, views, 3.0)
+    torch.cuda.synchronize()
+    got = img.cpu().numpy()
+    for k in range(3):
+        idx = [i for i, m in enumerate(vm) if m == k]
+        alone = ops.project_forward(*dm[k], views.subset(idx), 3.0, ops.Plan())
+        torch.cuda.synchronize()
+        a = alone.cpu().numpy()
+        assert np.abs(a - got[idx]).max() <= 1e-5 * max(float(np.abs(a).max()), 1e-30)
+        if models[k].n:
+            ov = [oracle.cone_view(th[i], 13.64, 20.46, 56, 44, 0.045) for i in idx]
+            v, _ = parity.forward_violation(got[idx], oracle.project(models[k], ov))
+            print(f"multi-model view set of model {k}: worst tolerance ratio {v:.3g}", flush=True)
+            assert v <= 1.0
+        else:
+            assert not got[idx].any()
+    from paper_2405_20693_amd._native import GsError
+    with pytest.raises(GsError, match="GS_EINVAL"):
+        ops.project_forward_multi(dm, [0, 1, 3, 0, 0, 0, 0], views, 3.0)
+
+
 def test_results_same_alone_and_in_the_mix(ops):
     models = [scenes.random_scene(81, 1500, lo=0.02, hi=0.1), scenes.random_scene(82, 900, lo=0.03, hi=0.12)]
     dm = [_dev(m) for m in models]
@@ -149,3 +181,43 @@ def test_serving_a_c4_sized_model(ops):
     v, _ = parity.forward_violation(part, oracle.voxelize(big, sg))
     print(f"c4-sized model, 24^3 of the 128^3 query: worst tolerance ratio {v:.3g}", flush=True)
     assert v <= 1.0
+
+
+def test_continuous_workspace_stays_within_the_budget(ops):
+    """Continuous batching reserves each worker's workspace from its share of
+    the HBM budget when a run starts: the reservation is at most the budget,
+    the device memory the run takes is that reservation, and requests of
+    several models share launches."""
+    models = [scenes.random_scene(90 + k, 600 + 400 * k, lo=0.02, hi=0.1) for k in range(4)]
+    dm = [_dev(m) for m in models]
+    budget = 96 << 20
+    srv = ops.Server(n_workers=2, batching=True, max_batch_views=32, hbm_budget_bytes=budget)
+    for m in dm:
+        srv.add_model(*m)
+    rng = np.random.default_rng(12)
+    reqs = []
+    for i in range(40):
+        nv = int(rng.integers(1, 6))
+        th = rng.uniform(0, 6.28) + np.arange(nv) * 6.28 / nv
+        reqs.append({"kind": "project", "model": int(rng.integers(0, 4)), "arrival_s": 0.0,
+                     "views": ops.Views.cone(th, 13.64, 20.46, 64, 64, 0.04),
+                     "out": torch.empty((nv, 64, 64), device="cuda")})
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    res, wall = srv.run(reqs, time_scale=0.0)
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    used = srv.reserved_bytes()
+    print(f"budget {budget}, reserved {used}, device memory taken {free0 - free1}", flush=True)
+    assert 0 < used <= budget
+    assert free0 - free1 <= budget + (64 << 20)  # allocation granularity
+    assert all(r["status"] == 0 for r in res)
+    batched = [i for i, r in enumerate(res) if r["batch_size"] > 1]
+    assert batched
+    assert any(len({reqs[j]["model"] for j in range(len(reqs))
+                    if res[j]["start_s"] == res[i]["start_s"]}) > 1 for i in batched)
+    for r in reqs[:8]:
+        alone = ops.project_forward(*dm[r["model"]], r["views"], 3.0, ops.Plan())
+        torch.cuda.synchronize()
+        a = alone.cpu().numpy()
+        assert np.abs(a - r["out"].cpu().numpy()).max() <= 1e-5 * max(float(np.abs(a).max()), 1e-30)
