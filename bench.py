@@ -169,7 +169,7 @@ def serving_measure(n_requests, fracs, models=None):
         log("generating 16 serving models ...")
         models = [[torch.from_numpy(a).to(dev) for a in (m.mean, m.scale, m.quat, m.density)]
                   for m in workloads.c4_models()]
-    servers = {"continuous": ops.Server(n_workers=4, batching=True, max_batch_views=256),
+    servers = {"continuous": ops.Server(n_workers=4, batching=True, max_batch_views=64),
                "per_request": ops.Server(n_workers=1, batching=False)}
     for srv in servers.values():
         for m in models:
@@ -222,7 +222,8 @@ def serving_measure(n_requests, fracs, models=None):
     return {"saturation": sat, "loads": loads, "requests_per_point": n_requests,
             "mix": "80% projections (1-64 views, 256^2@1.5mm or 512^2@0.75mm), "
                    "20% 128^3 sub-volumes of a 256^3 grid",
-            "continuous": "4 workers (streams), same-model projection merging up to 256 views",
+            "continuous": "4 workers (streams), 2 batches in flight each, projections of one model "
+                          "size class merged across models up to 64 views per launch",
             "per_request": "1 worker, one request per launch"}
 
 

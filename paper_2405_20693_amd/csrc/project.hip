@@ -266,8 +266,8 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
       s_fa[tid] = -r.c00;
       s_fb[tid] = -r.c01;
       s_fc[tid] = -r.c11;
-      s_ia[tid] = -0.5f / r.c00;
-      s_ic[tid] = -0.5f / r.c11;
+      s_ia[tid] = -0.5f * frcp(r.c00);
+      s_ic[tid] = -0.5f * frcp(r.c11);
       __syncthreads();
       for (uint32_t r0 = 0; r0 < total;) {
         const int jA = entry_owner(s_off, r0);  // first Gaussian of the round (uniform)
@@ -371,9 +371,10 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
   // entry's sub-tile mask
   __shared__ float4 s_r0[kBlock], s_r1[kBlock];
   __shared__ uint8_t s_m[kBlock];
-  // per wave: the kept records' coefficients, compacted, two float4 each
+  // per wave: the kept records' coefficients, compacted, two float4 each in
+  // two arrays, so that the eight groups read eight consecutive float4
   // (multiplicative records from the front, per-pixel exp2 records from the back)
-  __shared__ float4 s_k[4][64][2];
+  __shared__ float4 s_k[4][2][64];
   const int wi = xcd_remap(blockIdx.x, gridDim.x);
   const int item = wi / a.parts, part = wi - item * a.parts;
   const int v = item / a.T, t = item - v * a.T;
@@ -446,14 +447,14 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
       const int nc = __popcll(mc), ne = __popcll(me);
       if (hit) {
         const int pos = chain ? lanes_below(mc) : 63 - lanes_below(me);
-        s_k[w][pos][0] = k0;
-        s_k[w][pos][1] = k1;
+        s_k[w][0][pos] = k0;
+        s_k[w][1][pos] = k1;
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       for (int r = grp; r < nc; r += 8) {
-        const float4 a0 = s_k[w][r][0], a1 = s_k[w][r][1];
+        const float4 a0 = s_k[w][0][r], a1 = s_k[w][1][r];
         const float q0 = fmaf(a0.z, lxx, fmaf(a0.y, lx, a0.x));
         const float d0 = fmaf(a1.x, lx, a0.w);
         float e = copysignf(__builtin_amdgcn_exp2f(q0), a1.z);
@@ -467,7 +468,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
         }
       }
       for (int r = grp; r < ne; r += 8) {
-        const float4 a0 = s_k[w][63 - r][0], a1 = s_k[w][63 - r][1];
+        const float4 a0 = s_k[w][0][63 - r], a1 = s_k[w][1][63 - r];
         float q = fmaf(a0.z, lxx, fmaf(a0.y, lx, a0.x));
         float d = fmaf(a1.x, lx, a0.w);
 #pragma unroll
@@ -482,7 +483,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
     }
   }
   // the eight groups' sums of each pixel (lane x + 8 y), added in group order
-  float *red = reinterpret_cast<float *>(&s_k[w][0][0]);
+  float *red = reinterpret_cast<float *>(&s_k[w][0][0]);  // 512 floats per wave
 #pragma unroll
   for (int y = 0; y < kSub; ++y) red[grp * 64 + y * kSub + (lane & 7)] = acc[y];
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -890,9 +891,9 @@ __global__ __launch_bounds__(kBlock) void k_proj_chain(ProjArgs a,
       const float gm = gmu * (-0.5f * P.mu / P.m);
       float gd[3] = {0.f, 0.f, 0.f};
       for (int j = 0; j < 3; ++j) {
-        const float is2 = 1.f / (G.s[j] * G.s[j]);
+        const float is1 = frcp(G.s[j]), is2 = is1 * is1;
         const float gr = gm * 2.f * P.r[j] * is2;
-        gs[j] += gm * (-2.f * P.r[j] * P.r[j] * is2 / G.s[j]);
+        gs[j] += gm * (-2.f * P.r[j] * P.r[j] * is2 * is1);
         for (int i = 0; i < 3; ++i) {
           gR[3 * i + j] += P.d[i] * gr;
           gd[i] += G.R[3 * i + j] * gr;
@@ -906,7 +907,7 @@ __global__ __launch_bounds__(kBlock) void k_proj_chain(ProjArgs a,
         for (int aa = 0; aa < 3; ++aa)
           gu[aa] = W[3 * aa] * gd[0] + W[3 * aa + 1] * gd[1] + W[3 * aa + 2] * gd[2];
         const float ug = P.u[0] * gu[0] + P.u[1] * gu[1] + P.u[2] * gu[2];
-        const float il = 1.f / P.l;
+        const float il = frcp(P.l);
         for (int aa = 0; aa < 3; ++aa) gt[aa] += (gu[aa] - P.u[aa] * ug) * il;
         // JW = J2 W
         float gJ[6];
@@ -914,7 +915,7 @@ __global__ __launch_bounds__(kBlock) void k_proj_chain(ProjArgs a,
           for (int k = 0; k < 3; ++k)
             gJ[3 * aa + k] = gJW[3 * aa] * W[3 * k] + gJW[3 * aa + 1] * W[3 * k + 1] +
                              gJW[3 * aa + 2] * W[3 * k + 2];
-        const float L = V.L_SD, t0 = P.t[0], t1 = P.t[1], inv = 1.f / P.t[2];
+        const float L = V.L_SD, t0 = P.t[0], t1 = P.t[1], inv = frcp(P.t[2]);
         const float Li2 = L * inv * inv;
         gt[0] += -gJ[2] * Li2;
         gt[1] += -gJ[5] * Li2;

@@ -230,10 +230,12 @@ __global__ __launch_bounds__(kBlock) void k_ssim_coeffs(const float *__restrict_
     const float sxx = m[2][o] - mx * mx, syy = m[3][o] - my * my, sxy = m[4][o] - mx * my;
     const float A1 = 2.f * mx * my + kC1, A2 = 2.f * sxy + kC2;
     const float B1 = mx * mx + my * my + kC1, B2 = sxx + syy + kC2;
-    const float iB = 1.f / (B1 * B2);
+    // one hardware reciprocal (about 1 ulp) serves the three quotients:
+    // 1/B1 = B2/(B1 B2), 1/B2 = B1/(B1 B2)
+    const float iB = __builtin_amdgcn_rcpf(B1 * B2);
     const float S = A1 * A2 * iB;
-    const float dmx = 2.f * my * A2 * iB - 2.f * mx * S / B1;
-    const float dsxx = -S / B2;
+    const float dmx = 2.f * my * A2 * iB - 2.f * mx * S * (B2 * iB);
+    const float dsxx = -S * (B1 * iB);
     const float dsxy = 2.f * A1 * iB;
     const int64_t off = (int64_t)img * h * w + (int64_t)gy * w + gx;
     if (coef) {
@@ -362,10 +364,12 @@ __global__ __launch_bounds__(kBlock) void k_ssim_fused(const float *__restrict__
     const float sxx = m[2][o] - mx * mx, syy = m[3][o] - my * my, sxy = m[4][o] - mx * my;
     const float A1 = 2.f * mx * my + kC1, A2 = 2.f * sxy + kC2;
     const float B1 = mx * mx + my * my + kC1, B2 = sxx + syy + kC2;
-    const float iB = 1.f / (B1 * B2);
+    // one hardware reciprocal (about 1 ulp) serves the three quotients:
+    // 1/B1 = B2/(B1 B2), 1/B2 = B1/(B1 B2)
+    const float iB = __builtin_amdgcn_rcpf(B1 * B2);
     const float S = A1 * A2 * iB;
-    const float dmx = 2.f * my * A2 * iB - 2.f * mx * S / B1;
-    const float dsxx = -S / B2;
+    const float dmx = 2.f * my * A2 * iB - 2.f * mx * S * (B2 * iB);
+    const float dsxx = -S * (B1 * iB);
     const float dsxy = 2.f * A1 * iB;
     dv[0][o] = dmx - 2.f * mx * dsxx - my * dsxy;
     dv[1][o] = dsxx;
