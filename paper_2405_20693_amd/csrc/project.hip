@@ -342,17 +342,18 @@ void launch_proj_scatter(const ProjArgs &a, const Rec2 *rec, const uint32_t *his
 // ------------------------------------------------------- render forward --
 
 // One workgroup per (view, 16x16 tile); wave w owns the 8x8 sub-tile
-// (w & 1, w >> 1).  The tile's records are staged in LDS in batches of 256.
-// For each chunk of 64 records, lane i takes record i if its entry's mask
-// marks the wave's sub-tile (set by the scatter) and rewrites it relative to
-// the sub-tile centre: with x, y the pixel offsets from the centre,
+// (w & 1, w >> 1).  The tile's records are staged in LDS in batches of 256,
+// each expanded once about the tile centre.  For each chunk of 64 records,
+// lane i takes record i if its entry's mask marks the wave's sub-tile (set by
+// the scatter) and shifts the expansion to the sub-tile centre: with x, y the
+// pixel offsets from that centre,
 //   q' + log2|rho_hat| = A0 + A1 x + c00 x^2          on the first row,
 // stepping down a column by D(y) = B0 + c01 x, D itself by 2 c11.  The kept
 // records are compacted and dealt to the wave's eight 8-lane groups in turn;
 // each lane evaluates one column of eight pixels.  Where every value of
 // e = exp2(q') over the sub-tile is a normal FP32 number (form at most
-// kFwdChainRange there, its maximum being at a corner, and |rho_hat| not
-// tiny), e is stepped down the column by multiplication, e *= exp2(D),
+// kFwdChainRange there, its maximum being at a corner, where the exponent is
+// least, and |rho_hat| not tiny), e is stepped down the column by multiplication, e *= exp2(D),
 // exp2(D) *= exp2(2 c11): two exp2 per column instead of eight; the sign of
 // rho_hat rides on e and the cutoff becomes |e| >= exp2(threshold).  Other
 // records keep exp2 per pixel with q' forward-differenced; the two kinds are
@@ -367,9 +368,13 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
                                                        const uint32_t *__restrict__ tile_start,
                                                        float *__restrict__ image,
                                                        float *__restrict__ partial) {
-  // staged records: (pu, pv, c00, c01), (c11, rho, log2|rho|, -) and the
-  // entry's sub-tile mask
+  // staged records, relative to the tile centre: (K0, K1, K2, c00) of the
+  // exponent q' + log2|rho_hat| = K0 + K1 x + K2 y + c00 x^2 + c01 x y + c11 y^2,
+  // (c01, c11, exp2(2 c11), sign(rho_hat) exp2(threshold + log2|rho_hat|)),
+  // (threshold + log2|rho_hat|, the least exponent the multiplicative walk
+  // accepts), and the entry's sub-tile mask (empty for a zero density)
   __shared__ float4 s_r0[kBlock], s_r1[kBlock];
+  __shared__ float2 s_r2[kBlock];
   __shared__ uint8_t s_m[kBlock];
   // per wave: the kept records' coefficients, compacted, two float4 each in
   // two arrays, so that the eight groups read eight consecutive float4
@@ -383,7 +388,10 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
   const int sx0 = tx * kTile + (w & 1) * kSub, sy0 = ty * kTile + (w >> 1) * kSub;
   const int px = sx0 + (lane & 7), py = sy0 + (lane >> 3);
   const float hs = 0.5f * (kSub - 1);
-  const float cxs = (float)sx0 + hs, cys = (float)sy0 + hs;
+  // the tile centre, and the sub-tile centre relative to it
+  const float cxt = (float)(tx * kTile) + 0.5f * (kTile - 1), cyt = (float)(ty * kTile) + 0.5f * (kTile - 1);
+  const float du = (float)((w & 1) * kSub) + hs - 0.5f * (kTile - 1);
+  const float dv = (float)((w >> 1) * kSub) + hs - 0.5f * (kTile - 1);
   // the lane's column: x = lane & 7 of its group's copy of the sub-tile
   const int grp = lane >> 3;
   const float lx = (float)(lane & 7) - hs, lxx = lx * lx;
@@ -401,46 +409,49 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
     const int n = (int)min((uint32_t)kBlock, end - base);
     __syncthreads();
     if (tid < n) {
+      // once per record: its exponent relative to the tile centre
       const uint32_t ex = ex_next;
       const float4 *p = reinterpret_cast<const float4 *>(rv + (ex & kEntryIndexMask));
       const float4 r0 = p[0], r1 = p[1];
-      s_r0[tid] = r0;
-      s_r1[tid] = make_float4(r1.x, r1.y, __log2f(fabsf(r1.y)), 0.f);
-      s_m[tid] = (uint8_t)(ex >> kEntryMaskShift);
+      const float c00 = r0.z, c01 = r0.w, c11 = r1.x, rho = r1.y;
+      const float lr = __log2f(fabsf(rho));
+      const float U = r0.x - cxt, V = r0.y - cyt;
+      const float K0 = U * (c00 * U + c01 * V) + c11 * V * V + lr;
+      const float K1 = -(2.f * c00 * U + c01 * V), K2 = -(c01 * U + 2.f * c11 * V);
+      s_r0[tid] = make_float4(K0, K1, K2, c00);
+      s_r1[tid] = make_float4(c01, c11, __builtin_amdgcn_exp2f(2.f * c11),
+                              copysignf(__builtin_amdgcn_exp2f(thr + lr), rho));
+      s_r2[tid] = make_float2(thr + lr, fmaxf(lr, 0.f) - kFwdChainRange);
+      s_m[tid] = rho != 0.f ? (uint8_t)(ex >> kEntryMaskShift) : (uint8_t)0;
     }
     ex_next = base + kBlock + tid < end ? list[base + kBlock + tid].x : 0u;
     __syncthreads();
     for (int c0 = 0; c0 < n; c0 += 64) {
       const int i = c0 + lane;
-      bool hit = false, chain = false;
+      const bool hit = i < n && ((s_m[i] >> w) & 1u);
+      bool chain = false;
       float4 k0, k1;
-      if (i < n && ((s_m[i] >> w) & 1u)) {
+      if (hit) {
+        // the exponent relative to the sub-tile centre (the tile's
+        // expansion shifted by (du, dv)): on the first row
+        //   A0 + A1 x + c00 x^2, stepping down a column by B0 + c01 x
         const float4 r0 = s_r0[i], r1 = s_r1[i];
-        const float c00 = r0.z, c01 = r0.w, c11 = r1.x, rho = r1.y;
-        const float u = r0.x - cxs, vv = r0.y - cys;  // centre relative to the sub-tile centre
-        hit = rho != 0.f;
-        if (hit) {
-          const float lr = r1.z;
-          const float K0 = u * (c00 * u + c01 * vv) + c11 * vv * vv + lr;
-          const float K1 = -(2.f * c00 * u + c01 * vv);
-          const float K2 = -(c01 * u + 2.f * c11 * vv);
-          const float A0 = K0 - hs * K2 + hs * hs * c11, A1 = K1 - hs * c01;
-          const float B0 = K2 + c11 * (1.f - 2.f * hs);
-          // largest positive form -q over the sub-tile (at a corner)
-          float fmax = 0.f;
-#pragma unroll
-          for (int cx = 0; cx < 2; ++cx)
-#pragma unroll
-            for (int cy = 0; cy < 2; ++cy) {
-              const float dx = (cx ? hs : -hs) - u, dy = (cy ? hs : -hs) - vv;
-              fmax = fmaxf(fmax, -(dx * (c00 * dx + c01 * dy) + c11 * dy * dy));
-            }
-          chain = fmax + fmaxf(-lr, 0.f) <= kFwdChainRange;
-          k0 = make_float4(A0, A1, c00, B0);
-          k1 = chain ? make_float4(c01, __builtin_amdgcn_exp2f(2.f * c11),
-                                   copysignf(__builtin_amdgcn_exp2f(thr + lr), rho), 0.f)
-                     : make_float4(c01, 2.f * c11, thr + lr, rho > 0.f ? 1.f : -1.f);
-        }
+        const float2 r2 = s_r2[i];
+        const float c00 = r0.w, c01 = r1.x, c11 = r1.y;
+        const float K1 = fmaf(2.f * c00, du, fmaf(c01, dv, r0.y));
+        const float K2 = fmaf(c01, du, fmaf(2.f * c11, dv, r0.z));
+        const float K0 = r0.x + du * r0.y + dv * r0.z + du * (c00 * du + c01 * dv) + c11 * dv * dv;
+        const float A0 = K0 - hs * K2 + hs * hs * c11, A1 = K1 - hs * c01;
+        const float B0 = K2 + c11 * (1.f - 2.f * hs);
+        // the least exponent over the sub-tile is at a corner (+-hs, +-hs):
+        // P + c +- a on one diagonal, P - c +- b on the other
+        const float P = fmaf(hs * hs, c00 + c11, K0);
+        const float ea = hs * (K1 + K2), eb = hs * (K1 - K2), ec = hs * hs * c01;
+        const float qmin = P + fminf(ec - fabsf(ea), -ec - fabsf(eb));
+        chain = qmin >= r2.y;
+        k0 = make_float4(A0, A1, c00, B0);
+        k1 = chain ? make_float4(c01, r1.z, r1.w, 0.f)
+                   : make_float4(c01, 2.f * c11, r2.x, copysignf(1.f, r1.w));
       }
       // compact: multiplicative records from the front, the others from the back
       const uint64_t mc = __ballot(hit && chain), me = __ballot(hit && !chain);
