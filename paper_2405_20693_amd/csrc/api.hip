@@ -589,19 +589,18 @@ gs_status check_loss_image(const float *render, const float *measured, int32_t n
   if (!std::isfinite(lambda_ssim)) return fail(GS_EINVAL, "lambda_ssim not finite");
   const int64_t tiles = (int64_t)n_img * ((h + 31) / 32) * ((w + 31) / 32);
   if (tiles > 0x7fffffffLL) return fail(GS_EUNSUPPORTED, "more than 2^31-1 tiles of 32 x 32");
-  *nb = ssim_num_blocks(n_img, h, w);
+  if ((int64_t)h * w >= (int64_t)1 << 29) return fail(GS_EUNSUPPORTED, "images of 2^29 pixels or more");
+  *nb = loss_image_blocks(n_img, h, w);  // at most the number of 32 x 32 tiles
   return GS_OK;
 }
 
-// The SSIM + L1 kernel writes one pair of partial sums per 32 x 32 tile; the
-// finish kernel adds them in a fixed order.
+// The SSIM + L1 kernel writes one pair of partial sums per wavefront (the
+// same kernel with or without the gradient, so the loss is the same number);
+// the finish kernel adds them in a fixed order.
 void launch_loss_image(const float *render, const float *measured, int n_img, int h, int w,
                        float lambda_ssim, float *loss_out, float *grad, int nb, float *partials,
                        hipStream_t s) {
-  if (grad)
-    launch_ssim_fused(render, measured, n_img, h, w, lambda_ssim, grad, partials, s);
-  else
-    launch_ssim_coeffs(render, measured, n_img, h, w, nullptr, partials, s);
+  launch_ssim_march(render, measured, n_img, h, w, lambda_ssim, grad, partials, s);
   launch_loss_finish(partials, nb, n_img, h, w, lambda_ssim, loss_out, s);
 }
 
@@ -811,7 +810,7 @@ gs_status reserve_layout(gs_plan *p, const gs_reserve *r, bool staging, Take tak
     }
     // render parts x tiles stays below 8192 + tiles
     GS_TRY(take(p->p_fpart, 4 * (size_t)kBlock * (size_t)(8192 + VT)));
-    GS_TRY(take(p->l_part, 8 * (size_t)ssim_num_blocks((int)V, r->height, r->width)));
+    GS_TRY(take(p->l_part, 8 * (size_t)loss_image_blocks((int)V, r->height, r->width)));
     for (int k = 0; staging && k < gs_plan::kStageRing; ++k) {
       const size_t bytes = (sizeof(DevView) + sizeof(ViewSet)) * (size_t)V;
       if (p->stage_cap[k] < bytes) {
@@ -1203,10 +1202,14 @@ gs_status gs_loss_image_noalloc(const float *render, const float *measured, int3
                                 float *grad, hipStream_t stream) {
   int nb = 0;
   GS_TRY(check_loss_image(render, measured, n_img, h, w, lambda_ssim, loss_out, &nb));
-  if (nb > kNoAllocLossTiles)
-    return fail(GS_EUNSUPPORTED, "n_img x ceil(h/32) x ceil(w/32) = " + std::to_string(nb) +
+  // the limit is stated in tiles of 32 x 32; the kernel writes at most one
+  // pair of partial sums per tile
+  const int64_t tiles = (int64_t)n_img * ((h + 31) / 32) * ((w + 31) / 32);
+  if (tiles > kNoAllocLossTiles)
+    return fail(GS_EUNSUPPORTED, "n_img x ceil(h/32) x ceil(w/32) = " + std::to_string(tiles) +
                                      " tiles exceeds the " + std::to_string(kNoAllocLossTiles) +
                                      " of the static buffer");
+  if (nb > tiles) return fail(GS_EUNSUPPORTED, "loss partial sums exceed the tile count");
   float *part = nullptr;
   GS_TRY(noalloc_scratch(&part));
   launch_loss_image(render, measured, n_img, h, w, lambda_ssim, loss_out, grad, nb, part, stream);

@@ -464,8 +464,9 @@ void launch_ssim_coeffs(const float *x, const float *y, int n, int h, int w, flo
                         float *partials, hipStream_t s);
 void launch_loss_finish(const float *partials, int n_part, int n, int h, int w, float lambda_ssim,
                         float *loss_out, hipStream_t s);
-void launch_ssim_fused(const float *x, const float *y, int n, int h, int w, float lambda_ssim,
+void launch_ssim_march(const float *x, const float *y, int n, int h, int w, float lambda_ssim,
                        float *grad, float *partials, hipStream_t s);
+int loss_image_blocks(int n, int h, int w);
 int ssim_num_blocks(int n, int h, int w);
 void launch_tv(const float *vol, int nx, int ny, int nz, float weight, float *grad, int accumulate,
                float *partials, int *n_part, hipStream_t s);
