@@ -12,6 +12,15 @@ constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn2 = 0.69314718055994531f;
 constexpr float kTwoPi = 6.2831853071795865f;
 
+// Orders one wavefront's LDS accesses across its lanes: a wave's LDS
+// operations execute in program order, so no wait is needed, only that the
+// compiler keep that order.
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Reciprocal by the hardware instruction (about 1 ulp; an IEEE division takes
 // ten instructions).  The projection chain evaluates a dozen per (view,
 // Gaussian), far inside the FP32 tolerances of every result.

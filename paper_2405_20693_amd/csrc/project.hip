@@ -357,7 +357,9 @@ void launch_proj_scatter(const ProjArgs &a, const Rec2 *rec, const uint32_t *his
 // exp2(D) *= exp2(2 c11): two exp2 per column instead of eight; the sign of
 // rho_hat rides on e and the cutoff becomes |e| >= exp2(threshold).  Other
 // records keep exp2 per pixel with q' forward-differenced; the two kinds are
-// queued apart, so a record's path is its own.  The pixel sums
+// queued apart, so a record's path is its own, and each queue runs in whole
+// passes of the eight groups, its remainder carried to the next chunk.  The
+// pixel sums
 // sign(rho_hat) exp2(...) over the kept records (a plain sum: Eq. 7 composes
 // 2D Gaussians additively, so the order is free); the groups' partial sums
 // are added in a fixed order at the end.
@@ -377,9 +379,15 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
   __shared__ float2 s_r2[kBlock];
   __shared__ uint8_t s_m[kBlock];
   // per wave: the kept records' coefficients, compacted, two float4 each in
-  // two arrays, so that the eight groups read eight consecutive float4
-  // (multiplicative records from the front, per-pixel exp2 records from the back)
-  __shared__ float4 s_k[4][2][64];
+  // two arrays, so that the eight groups read eight consecutive float4:
+  // multiplicative records queue from the front, per-pixel exp2 records from
+  // the back.  Each queue is evaluated in whole passes of eight records; up
+  // to seven left over wait at its head for the next chunk, so that only the
+  // last pass of the tile list runs part-filled (64 new records and two
+  // remainders of seven fit the 78 places; 20 KB in all keeps eight
+  // workgroups per CU)
+  constexpr int kQ = 78;
+  __shared__ float4 s_k[4][2][kQ];
   const int wi = xcd_remap(blockIdx.x, gridDim.x);
   const int item = wi / a.parts, part = wi - item * a.parts;
   const int v = item / a.T, t = item - v * a.T;
@@ -404,6 +412,38 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
 #pragma unroll
   for (int y = 0; y < kSub; ++y) acc[y] = 0.f;
   // the next batch's entries are loaded while this batch renders
+  // the queues' first n records, dealt to the eight groups in turn
+  auto chain_pass = [&](int n) {
+    for (int r = grp; r < n; r += 8) {
+      const float4 a0 = s_k[w][0][r], a1 = s_k[w][1][r];
+      const float q0 = fmaf(a0.z, lxx, fmaf(a0.y, lx, a0.x));
+      const float d0 = fmaf(a1.x, lx, a0.w);
+      float e = copysignf(__builtin_amdgcn_exp2f(q0), a1.z);
+      float rr = __builtin_amdgcn_exp2f(d0);
+      const float et = fabsf(a1.z), R = a1.y;
+#pragma unroll
+      for (int y = 0; y < kSub; ++y) {
+        acc[y] += (fabsf(e) >= et) ? e : 0.f;
+        e *= rr;
+        rr *= R;
+      }
+    }
+  };
+  auto pixel_pass = [&](int n) {
+    for (int r = grp; r < n; r += 8) {
+      const float4 a0 = s_k[w][0][kQ - 1 - r], a1 = s_k[w][1][kQ - 1 - r];
+      float q = fmaf(a0.z, lxx, fmaf(a0.y, lx, a0.x));
+      float d = fmaf(a1.x, lx, a0.w);
+#pragma unroll
+      for (int y = 0; y < kSub; ++y) {
+        const float ev = (q >= a1.z) ? __builtin_amdgcn_exp2f(q) : 0.f;
+        acc[y] = fmaf(a1.w, ev, acc[y]);
+        q += d;
+        d += a1.y;
+      }
+    }
+  };
+  int qc = 0, qe = 0;  // records waiting in the two queues (wave-uniform)
   uint32_t ex_next = beg + tid < end ? list[beg + tid].x : 0u;
   for (uint32_t base = beg; base < end; base += kBlock) {
     const int n = (int)min((uint32_t)kBlock, end - base);
@@ -455,44 +495,37 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
       }
       // compact: multiplicative records from the front, the others from the back
       const uint64_t mc = __ballot(hit && chain), me = __ballot(hit && !chain);
-      const int nc = __popcll(mc), ne = __popcll(me);
       if (hit) {
-        const int pos = chain ? lanes_below(mc) : 63 - lanes_below(me);
+        const int pos = chain ? qc + lanes_below(mc) : kQ - 1 - (qe + lanes_below(me));
         s_k[w][0][pos] = k0;
         s_k[w][1][pos] = k1;
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      for (int r = grp; r < nc; r += 8) {
-        const float4 a0 = s_k[w][0][r], a1 = s_k[w][1][r];
-        const float q0 = fmaf(a0.z, lxx, fmaf(a0.y, lx, a0.x));
-        const float d0 = fmaf(a1.x, lx, a0.w);
-        float e = copysignf(__builtin_amdgcn_exp2f(q0), a1.z);
-        float rr = __builtin_amdgcn_exp2f(d0);
-        const float et = fabsf(a1.z), R = a1.y;
-#pragma unroll
-        for (int y = 0; y < kSub; ++y) {
-          acc[y] += (fabsf(e) >= et) ? e : 0.f;
-          e *= rr;
-          rr *= R;
-        }
+      qc += __popcll(mc);
+      qe += __popcll(me);
+      wave_lds_order();
+      const int fc = qc & ~7, fe = qe & ~7;  // whole passes
+      chain_pass(fc);
+      pixel_pass(fe);
+      wave_lds_order();
+      // the remainders move to the queue heads (disjoint from their sources:
+      // fewer than eight records, moved only past a whole pass)
+      if (fc > 0 && lane < qc - fc) {
+        s_k[w][0][lane] = s_k[w][0][fc + lane];
+        s_k[w][1][lane] = s_k[w][1][fc + lane];
       }
-      for (int r = grp; r < ne; r += 8) {
-        const float4 a0 = s_k[w][0][63 - r], a1 = s_k[w][1][63 - r];
-        float q = fmaf(a0.z, lxx, fmaf(a0.y, lx, a0.x));
-        float d = fmaf(a1.x, lx, a0.w);
-#pragma unroll
-        for (int y = 0; y < kSub; ++y) {
-          const float ev = (q >= a1.z) ? __builtin_amdgcn_exp2f(q) : 0.f;
-          acc[y] = fmaf(a1.w, ev, acc[y]);
-          q += d;
-          d += a1.y;
-        }
+      if (fe > 0 && lane < qe - fe) {
+        s_k[w][0][kQ - 1 - lane] = s_k[w][0][kQ - 1 - fe - lane];
+        s_k[w][1][kQ - 1 - lane] = s_k[w][1][kQ - 1 - fe - lane];
       }
-      __builtin_amdgcn_wave_barrier();  // the next chunk overwrites this wave's coefficients
+      qc -= fc;
+      qe -= fe;
+      wave_lds_order();
     }
   }
+  // the last, part-filled passes
+  chain_pass(qc);
+  pixel_pass(qe);
+  wave_lds_order();
   // the eight groups' sums of each pixel (lane x + 8 y), added in group order
   float *red = reinterpret_cast<float *>(&s_k[w][0][0]);  // 512 floats per wave
 #pragma unroll

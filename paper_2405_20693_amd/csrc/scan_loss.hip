@@ -322,12 +322,7 @@ __device__ __forceinline__ float rsrc_load(__amdgpu_buffer_rsrc_t r, uint32_t of
 }
 
 // The workgroup is one wavefront, whose LDS operations execute in program
-// order: ordering them needs no wait, only that the compiler keep the order.
-__device__ __forceinline__ void wave_lds_order() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
+// order (wave_lds_order keeps the compiler from reordering them).
 
 // One wavefront's state; the functions below are inlined into the kernel,
 // so it lives in registers (the rings are indexed by compile-time slots).
