@@ -240,7 +240,10 @@ GS_API gs_status gs_voxelize_bwd(const gs_gaussians *g, const gs_grid *grid, flo
  * window (sigma 1.5, normalised), zero padding, C1 = 0.01^2, C2 = 0.03^2.
  * loss_out (device, 3 floats): {total, l1, ssim}.
  * grad (device [n_img][h][w], may be NULL): d total / d render, overwritten.
- * plan must not be NULL (holds the per-tile partial sums). */
+ * The loss is the same number with or without grad (one kernel computes it).
+ * Images of 2^29 pixels or more return GS_EUNSUPPORTED.
+ * plan must not be NULL (holds the partial sums, one pair per wavefront of
+ * the loss kernel, summed in a fixed order). */
 GS_API gs_status gs_loss_image(const float *render, const float *measured, int32_t n_img, int32_t h,
                         int32_t w, float lambda_ssim, float *loss_out, float *grad, gs_plan *plan,
                         hipStream_t stream);
@@ -248,11 +251,11 @@ GS_API gs_status gs_loss_image(const float *render, const float *measured, int32
 /* For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.  Computes
  * exactly what gs_loss_image computes (same kernels, bitwise the same loss
- * and gradient), without a plan: the per-tile partial sums go to a static
- * device buffer inside the library, one per GPU, held until the process ends
- * (2 MiB: GS_LOSS_IMAGE_NOALLOC_TILES tiles of 32 x 32 pixels).  A stack of
- * more than that many tiles, n_img ceil(h/32) ceil(w/32), returns
- * GS_EUNSUPPORTED before any launch.  The call makes no hipMalloc, hipFree or
+ * and gradient), without a plan: the partial sums go to a static device
+ * buffer inside the library, one per GPU, held until the process ends (2 MiB:
+ * room for GS_LOSS_IMAGE_NOALLOC_TILES pairs; the kernel writes at most one
+ * pair per 32 x 32 tile).  A stack of more than that many tiles,
+ * n_img ceil(h/32) ceil(w/32), returns GS_EUNSUPPORTED before any launch.  The call makes no hipMalloc, hipFree or
  * other allocating call; the first call on a device looks up that device's
  * buffer address once.  Every call on one GPU shares its buffer: calls that
  * overlap on one GPU (streams or threads with no ordering between them) race
