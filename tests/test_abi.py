@@ -89,6 +89,15 @@ def test_argument_errors_are_caught_before_any_launch(native):
     assert st == 1
     st = lib.gs_plan_create(ctypes.c_void_p(1), None, None, ctypes.byref(ctypes.c_void_p()))
     assert st == 1  # alloc without free
+    # the image loss: sizes, and images of 2^29 pixels or more (the loss
+    # kernel addresses one image with 32-bit byte offsets)
+    d = ctypes.c_void_p(8)
+    st = lib.gs_loss_image(d, d, 1, 0, 16, ctypes.c_float(0.25), d, None, None, None)
+    assert st == 1  # GS_EINVAL
+    st = lib.gs_loss_image(d, d, 1, 1 << 15, 1 << 14, ctypes.c_float(0.25), d, None, None, None)
+    assert st == 5 and b"2^29" in lib.gs_last_error()
+    st = lib.gs_loss_image_noalloc(d, d, 1, 1 << 15, 1 << 14, ctypes.c_float(0.25), d, None, None)
+    assert st == 5
 
 
 def test_product_path_does_not_use_the_oracle():
