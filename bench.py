@@ -138,11 +138,21 @@ def stage_model(stages_ms, M, V, H, W, entries, pairs, vox_pairs, block):
         "loss_image": ("hbm", 12 * pix),
         "loss_tv": ("hbm", 8 * block ** 3),
     }
+    # HBM bytes the ALU-bound stages move at least: their inputs and outputs
+    # (records, tile lists, images, per-(view, Gaussian) 2D gradients; voxel
+    # records, the block)
+    nvox = block ** 3
+    io = {"render_fwd": 32 * V * M + 8 * entries + 4 * pix,
+          "render_bwd": 32 * V * M + 8 * entries + 4 * pix + 24 * V * M,
+          "vox_fwd": 64 * M + 4 * nvox,
+          "vox_bwd": 64 * M + 4 * nvox + 40 * M}
     out, t_floor = {}, 0.0
+    hbm_bytes = 0
     for k, ms in stages_ms.items():
         if k not in work:
             continue
         bound, w = work[k]
+        hbm_bytes += w if bound == "hbm" else io[k]
         peak = PEAK_SLOTS_PER_S if bound == "alu" else HBM_PEAK_BYTES_PER_S
         floor_s = w / peak
         t_floor += floor_s
@@ -151,7 +161,7 @@ def stage_model(stages_ms, M, V, H, W, entries, pairs, vox_pairs, block):
                   "achieved": round(w / (ms * 1e-3) / (1e12 if bound == "alu" else 1e9), 3),
                   "achieved_unit": "T slots/s" if bound == "alu" else "GB/s",
                   "frac": round(floor_s / (ms * 1e-3), 4)}
-    return out, t_floor * 1e3
+    return out, t_floor * 1e3, hbm_bytes
 
 
 def serving_measure(n_requests, fracs, models=None):
@@ -496,11 +506,17 @@ def main():
     except Exception as e:  # the probe is context, the line stands without it
         log(f"ALU probe failed: {e}")
     if pairs is not None:
-        stage_frac, t_floor_ms = stage_model(avg, g.n, views.n, views.height, views.width, entries,
-                                             pairs, vox_pairs, block)
+        stage_frac, t_floor_ms, hbm_bytes = stage_model(avg, g.n, views.n, views.height,
+                                                        views.width, entries, pairs, vox_pairs,
+                                                        block)
         floor = {"t_floor_ms": round(t_floor_ms, 4), "t_measured_ms": round(ms_per_step, 4),
                  "frac": round(t_floor_ms / ms_per_step, 4),
-                 "rule": "sum over stages of max(algorithmic bytes / 8 TB/s, VALU slots / peak)"}
+                 "rule": "sum over stages of max(algorithmic bytes / 8 TB/s, VALU slots / peak)",
+                 "hbm": {"bytes": int(hbm_bytes),
+                         "achieved_gbs": round(hbm_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+                         "frac": round(hbm_bytes / (ms_per_step * 1e-3) / HBM_PEAK_BYTES_PER_S, 4),
+                         "rule": "sum over stages of their algorithmic HBM bytes (ALU-bound stages: "
+                                 "their inputs and outputs) / (ms_per_step x 8 TB/s)"}}
         dom = "render_bwd"
         traffic = measured_traffic()
         ops_per_launch = pairs * SLOTS_PER_PAIR["bwd"]
