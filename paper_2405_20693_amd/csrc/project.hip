@@ -194,13 +194,22 @@ void launch_hist_colscan(int groups, int C, int T, uint32_t *hist, uint32_t *til
 // position is the tile's cursor plus the number of lower bits set, and the
 // entry holding the highest bit then advances the cursor and clears the mask.
 // Tiles are handled in windows of kScatterWindow so that masks and cursors
-// fit LDS.  Each entry carries the mask of the tile's 8x8 sub-tiles that the
+// fit LDS.  Detectors of more than 2048 tiles use 32-bit masks (rounds of at
+// most 32 Gaussians) so that three workgroups fit a CU; the lists are the
+// same with either width, only the rounds differ.  Each entry carries the mask of the tile's 8x8 sub-tiles that the
 // cutoff ellipse meets (exact minimum of the quadratic form over each
 // sub-tile's pixel-centre rectangle).
 constexpr int kScatterWindow = 4096;
 
-int proj_scatter_lds(int T) { return min(T, kScatterWindow) * 12; }
+constexpr int kScatterWideTiles = 2048;  // above this, 32-bit masks
 
+template <typename MaskT>
+int proj_scatter_lds(int T) { return min(T, kScatterWindow) * (int)(sizeof(MaskT) + 4); }
+
+__device__ inline int mask_popc(uint32_t m) { return __popc(m); }
+__device__ inline int mask_popc(unsigned long long m) { return __popcll(m); }
+
+template <typename MaskT>
 __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 *__restrict__ rec,
                                                          const uint32_t *__restrict__ hist,
                                                          const uint32_t *__restrict__ tile_start,
@@ -209,7 +218,8 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
                                                          uint32_t *__restrict__ offsets,
                                                          unsigned long long *ctl,
                                                          const unsigned long long *totals) {
-  extern __shared__ unsigned long long s_dyn[];  // window masks, then cursors
+  constexpr int kRoundG = 8 * (int)sizeof(MaskT);  // Gaussians per placement round
+  extern __shared__ unsigned long long s_dyn[];     // window masks, then cursors
   __shared__ uint32_t sh4[4];
   __shared__ uint32_t s_off[kBlock + 1];  // exclusive entry offsets of the 256 Gaussians
   __shared__ uint32_t s_org[kBlock];      // rectangle origin tx0 | ty0 << 16
@@ -218,8 +228,8 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
   __shared__ float s_ia[kBlock], s_ic[kBlock];
   const int c = blockIdx.x, v = blockIdx.y, tid = threadIdx.x;
   const int Tw = min(a.T, kScatterWindow);
-  unsigned long long *s_mask = s_dyn;
-  uint32_t *cur = reinterpret_cast<uint32_t *>(s_dyn + Tw);
+  MaskT *s_mask = reinterpret_cast<MaskT *>(s_dyn);
+  uint32_t *cur = reinterpret_cast<uint32_t *>(s_mask + Tw);
   if (c == 0 && v == 0 && tid == 0) {  // the binning kernels of this call have finished
     ctl[2] = ctl[0];
     ctl[0] = 0ull;
@@ -239,7 +249,7 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
     const int wn = min(Tw, a.T - w0);
     for (int t = tid; t < wn; t += kBlock) {
       cur[t] = ts[w0 + t] + h[w0 + t];
-      s_mask[t] = 0ull;
+      s_mask[t] = 0;
     }
     base = chunk_start[v * a.C + c];
     for (int k = 0; k < a.cpt; ++k) {
@@ -271,7 +281,7 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
       __syncthreads();
       for (uint32_t r0 = 0; r0 < total;) {
         const int jA = entry_owner(s_off, r0);  // first Gaussian of the round (uniform)
-        const uint32_t r1 = min(r0 + (uint32_t)kBlock, s_off[min(jA + 64, kBlock)]);
+        const uint32_t r1 = min(r0 + (uint32_t)kBlock, s_off[min(jA + kRoundG, kBlock)]);
         const uint32_t e = r0 + (uint32_t)tid;
         int t = 0, bit = 0;
         bool act = false;
@@ -303,20 +313,20 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
             }
             ent = make_uint2((uint32_t)(gk + j) | (m << kEntryMaskShift), base + e);
             bit = j - jA;
-            atomicOr(&s_mask[t], 1ull << bit);
+            atomicOr(&s_mask[t], (MaskT)1 << bit);
           }
         }
         __syncthreads();
-        unsigned long long mk = 0ull;
+        MaskT mk = 0;
         if (act) {
           mk = s_mask[t];
-          const uint32_t pos = cur[t] + (uint32_t)__popcll(mk & ((1ull << bit) - 1ull));
+          const uint32_t pos = cur[t] + (uint32_t)mask_popc((MaskT)(mk & (((MaskT)1 << bit) - 1)));
           if (pos < a.cap) list[pos] = ent;
         }
         __syncthreads();
-        if (act && (mk >> bit) == 1ull) {  // the round's last entry of this tile
-          cur[t] += (uint32_t)__popcll(mk);
-          s_mask[t] = 0ull;
+        if (act && (mk >> bit) == 1) {  // the round's last entry of this tile
+          cur[t] += (uint32_t)mask_popc(mk);
+          s_mask[t] = 0;
         }
         __syncthreads();
         r0 = r1;
@@ -335,8 +345,13 @@ void launch_proj_scatter(const ProjArgs &a, const Rec2 *rec, const uint32_t *his
                          uint32_t *offsets, unsigned long long *ctl,
                          const unsigned long long *totals, hipStream_t s) {
   dim3 grid(a.C, a.V);
-  hipLaunchKernelGGL(k_proj_scatter, grid, dim3(kBlock), proj_scatter_lds(a.T), s, a, rec, hist,
-                     tile_start, chunk_start, list, offsets, ctl, totals);
+  if (a.T > kScatterWideTiles)
+    hipLaunchKernelGGL(k_proj_scatter<uint32_t>, grid, dim3(kBlock), proj_scatter_lds<uint32_t>(a.T),
+                       s, a, rec, hist, tile_start, chunk_start, list, offsets, ctl, totals);
+  else
+    hipLaunchKernelGGL(k_proj_scatter<unsigned long long>, grid, dim3(kBlock),
+                       proj_scatter_lds<unsigned long long>(a.T), s, a, rec, hist, tile_start,
+                       chunk_start, list, offsets, ctl, totals);
 }
 
 // ------------------------------------------------------- render forward --
