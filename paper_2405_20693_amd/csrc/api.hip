@@ -258,6 +258,10 @@ gs_status check_grid(const gs_grid *grid) {
   if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1 || grid->nx > 16384 || grid->ny > 16384 ||
       grid->nz > 16384)
     return fail(GS_EINVAL, "grid size out of 1..16384");
+  // the voxel binning keeps one z-layer of 8^3 tiles in LDS
+  if ((int64_t)((grid->nx + kVTile - 1) / kVTile) * ((grid->ny + kVTile - 1) / kVTile) >
+      kMaxTilesPerGroup)
+    return fail(GS_EUNSUPPORTED, "grid plane has more than 16384 tiles");
   for (int k = 0; k < 3; ++k) {
     if (!finite_pos(grid->spacing[k])) return fail(GS_EINVAL, "grid spacing must be > 0");
     if (!std::isfinite(grid->origin[k])) return fail(GS_EINVAL, "grid origin not finite");
@@ -995,12 +999,31 @@ gs_status gs_view_cone(double theta, float src_obj, float src_det, int32_t width
   return GS_OK;
 }
 
+// The projection kernels' size limits, checked before any plan or device
+// memory is touched: 16384 tiles of 16x16 per view, 2^28 - 1 Gaussians per
+// model (entries carry the index in 28 bits).
+static gs_status check_proj_limits(const gs_gaussians *g, const gs_gaussians *models,
+                                   const int32_t *view_model, const gs_view *views,
+                                   int32_t n_views) {
+  const int64_t T = (int64_t)((views[0].width + kTile - 1) / kTile) *
+                    ((views[0].height + kTile - 1) / kTile);
+  if (T > kMaxTilesPerGroup)
+    return fail(GS_EUNSUPPORTED, "detector has more than 16384 tiles of 16x16 pixels");
+  int64_t most = g->n;
+  if (models)
+    for (int v = 0; v < n_views; ++v) most = std::max<int64_t>(most, models[view_model[v]].n);
+  if (most > (int64_t)kEntryIndexMask)
+    return fail(GS_EUNSUPPORTED, "projection of more than 2^28-1 Gaussians in one call");
+  return GS_OK;
+}
+
 static gs_status project_fwd(const gs_gaussians *g, const gs_gaussians *models,
                              const int32_t *view_model, const gs_view *views, int32_t n_views,
                              float cutoff, float *image, gs_plan *plan, hipStream_t stream) {
   GS_TRY(check_views(views, n_views));
   GS_TRY(check_cutoff(cutoff));
   if (!image) return fail(GS_EINVAL, "image is NULL");
+  GS_TRY(check_proj_limits(g, models, view_model, views, n_views));
   TempPlan tp;
   if (!plan) {
     GS_TRY(gs_plan_create(nullptr, nullptr, nullptr, &tp.p));
@@ -1067,6 +1090,7 @@ static gs_status project_bwd(const gs_gaussians *g, const gs_view *views, int32_
   GS_TRY(check_gaussians(g));
   GS_TRY(check_views(views, n_views));
   GS_TRY(check_cutoff(cutoff));
+  GS_TRY(check_proj_limits(g, nullptr, nullptr, views, n_views));
   if (!grad_image) return fail(GS_EINVAL, "grad_image is NULL");
   if (!grads) return fail(GS_EINVAL, "grads is NULL");
   if (!plan) return fail(GS_EINVAL, "plan is NULL");

@@ -98,6 +98,22 @@ def test_argument_errors_are_caught_before_any_launch(native):
     assert st == 5 and b"2^29" in lib.gs_last_error()
     st = lib.gs_loss_image_noalloc(d, d, 1, 1 << 15, 1 << 14, ctypes.c_float(0.25), d, None, None)
     assert st == 5
+    # the kernels' size limits, refused before any plan or device memory
+    g.mean = g.scale = g.quat = g.density = d
+    g.n = 1 << 28  # entries carry the Gaussian index in 28 bits
+    st = lib.gs_project_fwd(ctypes.byref(g), ctypes.byref(v), 1, 3.0, d, None, None)
+    assert st == 5 and b"2^28" in lib.gs_last_error()
+    g.n = 10
+    wide = native.GsView()
+    native.call("gs_view_cone", 0.0, 10.0, 20.0, 4096, 1040, 0.05, ctypes.byref(wide))
+    st = lib.gs_project_fwd(ctypes.byref(g), ctypes.byref(wide), 1, 3.0, d, None, None)
+    assert st == 5 and b"16384 tiles" in lib.gs_last_error()
+    big = native.GsGrid()
+    big.nx, big.ny, big.nz = 1040, 1040, 8
+    for k in range(3):
+        big.spacing[k] = 0.01
+    st = lib.gs_voxelize_fwd(ctypes.byref(g), ctypes.byref(big), 3.0, d, None, None)
+    assert st == 5 and b"16384 tiles" in lib.gs_last_error()
 
 
 def test_product_path_does_not_use_the_oracle():
