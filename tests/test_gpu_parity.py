@@ -299,6 +299,32 @@ def test_binning_and_results_are_bitwise_reproducible(ops):
             assert torch.equal(x, y)
 
 
+def test_wide_detector_binning(ops):
+    """A detector of more than 2048 tiles (1040 x 800: 3250), where the scatter
+    places entries with 32-bit tile masks: two calls give bitwise equal
+    images and gradients, and both match the oracle."""
+    g = scenes.random_scene(46, 2000, lo=0.005, hi=0.05, box=0.9)
+    views = ops.Views.cone([0.7], 13.64, 20.46, 1040, 800, 0.017)
+    ov = [oracle.cone_view(0.7, 13.64, 20.46, 1040, 800, 0.017)]
+    G = upstream(12, (1, 800, 1040))
+    t = _dev(g)
+    runs = []
+    for _ in range(2):
+        plan = ops.Plan()
+        img = ops.project_forward(*t, views, 3.0, plan)
+        gp = ops.project_backward(*t, views, torch.from_numpy(G).cuda(), plan, 3.0)
+        torch.cuda.synchronize()
+        runs.append((img.clone(),) + tuple(x.clone() for x in gp))
+    for x, y in zip(runs[0], runs[1]):
+        assert torch.equal(x, y)
+    v, _ = parity.forward_violation(runs[0][0].cpu().numpy(), oracle.project(g, ov))
+    _report("wide detector forward", v)
+    assert v <= 1.0
+    el, nr, det = parity.grad_violation(_np(runs[0][1:]), oracle.project_grad(g, ov, G, 3.0, with_scale=True))
+    _report("wide detector gradients", max(el, nr))
+    assert el <= 1.0 and nr <= 1.0
+
+
 # ----------------------------------------------------------------- losses --
 
 def test_image_loss(ops):
