@@ -814,7 +814,9 @@ gs_status reserve_layout(gs_plan *p, const gs_reserve *r, bool staging, Take tak
     }
     // render parts x tiles stays below 8192 + tiles
     GS_TRY(take(p->p_fpart, 4 * (size_t)kBlock * (size_t)(8192 + VT)));
-    GS_TRY(take(p->l_part, 8 * (size_t)loss_image_blocks((int)V, r->height, r->width)));
+    // the loss kernels write at most one pair of partial sums per 32 x 32
+    // tile, whichever of them a stack of up to V images takes
+    GS_TRY(take(p->l_part, 8 * (size_t)ssim_num_blocks((int)V, r->height, r->width)));
     for (int k = 0; staging && k < gs_plan::kStageRing; ++k) {
       const size_t bytes = (sizeof(DevView) + sizeof(ViewSet)) * (size_t)V;
       if (p->stage_cap[k] < bytes) {

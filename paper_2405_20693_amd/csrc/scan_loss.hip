@@ -269,6 +269,194 @@ void launch_ssim_coeffs(const float *x, const float *y, int n, int h, int w, flo
                      w, coef, partials);
 }
 
+// Loss and gradient in one pass per 32 x 32 output tile (stacks too small to
+// fill the chip with the marching kernel below; grad may be NULL).  The gradient at a
+// pixel needs the coefficient maps D1..D3 on a 5-pixel halo, and those need
+// the inputs on a further 5-pixel halo, so the workgroup stages x and y over
+// 52 x 52, computes the five blurred moments and D1..D3 over the 42 x 42
+// coefficient region (zero outside the image: the maps are only defined on
+// image pixels), then blurs the coefficients for its 32 x 32 outputs.  Each
+// plane is blurred separately (row pass to LDS, column pass to registers) to
+// keep LDS at about 32 KB; the coefficient maps overwrite the staged inputs.
+// grad = (sign(x - y) - lambda (blur(D1) + 2 x blur(D2) + y blur(D3))) / N;
+// partials[block] = {sum S, sum |x - y|} over the tile's image pixels.
+constexpr int kDW = kSW + 2 * kR;  // 42: coefficient region edge
+constexpr int kXW = kDW + 2 * kR;  // 52: input region edge
+constexpr int kF1 = 7;             // stage 1: outputs per row task and per column task
+constexpr int kF2 = 8;             // stage 2: outputs per row task
+constexpr int kR1 = 11, kRSeg = 4;  // stage 1 row pass: outputs per task, tasks per row
+static_assert(kR1 * kRSeg >= kDW && kR1 * (kRSeg - 1) < kDW, "row segments cover the row");
+
+__global__ __launch_bounds__(kBlock) void k_ssim_fused(const float *__restrict__ x,
+                                                       const float *__restrict__ y, int n, int h,
+                                                       int w, float lambda,
+                                                       float *__restrict__ grad,
+                                                       float *__restrict__ partials) {
+  __shared__ float s_in[2 * kXW * kXW];  // x, y over 52 x 52; later D1..D3 over 42 x 42
+  __shared__ float s_h[kXW * kDW];       // row-pass output of one plane
+  __shared__ float red[2][kBlock];
+  static_assert(3 * kDW * kDW <= 2 * kXW * kXW, "the coefficient maps fit the input buffer");
+  float *sx = s_in, *sy = s_in + kXW * kXW;
+  const int tiles_x = (w + kSW - 1) / kSW, tiles_y = (h + kSH - 1) / kSH;
+  const int b = blockIdx.x;
+  const int img = b / (tiles_x * tiles_y), tt = b - img * tiles_x * tiles_y;
+  const int ty = tt / tiles_x, tx = tt - ty * tiles_x;
+  const int X0 = tx * kSW, Y0 = ty * kSH;  // first output pixel
+  const int64_t ib = (int64_t)img * h * w;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kXW * kXW; i += kBlock) {
+    const int r = i / kXW, c = i - r * kXW;
+    const int gy = Y0 - 2 * kR + r, gx = X0 - 2 * kR + c;
+    const bool in = gx >= 0 && gx < w && gy >= 0 && gy < h;
+    sx[i] = in ? x[ib + (int64_t)gy * w + gx] : 0.f;
+    sy[i] = in ? y[ib + (int64_t)gy * w + gx] : 0.f;
+  }
+  __syncthreads();
+  // stage 1: blurred x, y, x^2, y^2, xy at the thread's 7 coefficient positions
+  // (column dc, rows dr0 .. dr0 + 6 of the 42 x 42 region; 252 threads)
+  const bool t1 = tid < (kDW / kF1) * kDW;
+  const int dc = tid % kDW, dr0 = (tid / kDW) * kF1;
+  float m[5][kF1];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    // row pass: 52 rows x 4 segments of kR1 outputs (the last one 9), one
+    // task per thread
+    if (tid < kXW * kRSeg) {
+      const int r = tid / kRSeg, c0 = (tid - r * kRSeg) * kR1;
+      float win[kR1 + kWin - 1];
+#pragma unroll
+      for (int k = 0; k < kR1 + kWin - 1; ++k) {
+        const bool in = c0 + k < kXW;  // the last segment's window ends at the row
+        const float xv = in ? sx[r * kXW + c0 + k] : 0.f, yv = in ? sy[r * kXW + c0 + k] : 0.f;
+        win[k] = q == 0 ? xv : q == 1 ? yv : q == 2 ? xv * xv : q == 3 ? yv * yv : xv * yv;
+      }
+#pragma unroll
+      for (int o = 0; o < kR1; ++o) {
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < kWin; ++k) acc = fmaf(c_win[k], win[o + k], acc);
+        if (c0 + o < kDW) s_h[r * kDW + c0 + o] = acc;
+      }
+    }
+    __syncthreads();
+    if (t1) {
+      float win[kF1 + kWin - 1];
+#pragma unroll
+      for (int k = 0; k < kF1 + kWin - 1; ++k) win[k] = s_h[(dr0 + k) * kDW + dc];
+#pragma unroll
+      for (int o = 0; o < kF1; ++o) {
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < kWin; ++k) acc = fmaf(c_win[k], win[o + k], acc);
+        m[q][o] = acc;
+      }
+    }
+    __syncthreads();
+  }
+  // SSIM, its derivative maps, and the tile's sums (interior positions only)
+  float ssum = 0.f, lsum = 0.f;
+  float dv[3][kF1];
+#pragma unroll
+  for (int o = 0; o < kF1; ++o) {
+    dv[0][o] = dv[1][o] = dv[2][o] = 0.f;
+    const int dr = dr0 + o;
+    const int gy = Y0 - kR + dr, gx = X0 - kR + dc;
+    if (!t1 || gx < 0 || gx >= w || gy < 0 || gy >= h) continue;
+    const float mx = m[0][o], my = m[1][o];
+    const float sxx = m[2][o] - mx * mx, syy = m[3][o] - my * my, sxy = m[4][o] - mx * my;
+    const float A1 = 2.f * mx * my + kC1, A2 = 2.f * sxy + kC2;
+    const float B1 = mx * mx + my * my + kC1, B2 = sxx + syy + kC2;
+    // one hardware reciprocal (about 1 ulp) serves the three quotients:
+    // 1/B1 = B2/(B1 B2), 1/B2 = B1/(B1 B2)
+    const float iB = __builtin_amdgcn_rcpf(B1 * B2);
+    const float S = A1 * A2 * iB;
+    const float dmx = 2.f * my * A2 * iB - 2.f * mx * S * (B2 * iB);
+    const float dsxx = -S * (B1 * iB);
+    const float dsxy = 2.f * A1 * iB;
+    dv[0][o] = dmx - 2.f * mx * dsxx - my * dsxy;
+    dv[1][o] = dsxx;
+    dv[2][o] = dsxy;
+    if (dr >= kR && dr < kR + kSH && dc >= kR && dc < kR + kSW) {
+      ssum += S;
+      const int i = (dr + kR) * kXW + dc + kR;
+      lsum += fabsf(sx[i] - sy[i]);
+    }
+  }
+  red[0][tid] = ssum;
+  red[1][tid] = lsum;
+  __syncthreads();  // the staged inputs are no longer read
+  if (grad) {
+    if (t1) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int o = 0; o < kF1; ++o) s_in[(q * kDW + dr0 + o) * kDW + dc] = dv[q][o];
+    }
+    __syncthreads();
+    // stage 2: blurred D1..D3 at 4 outputs per thread (column c, rows r0 .. r0 + 3)
+    const int c = tid & (kSW - 1), r0 = (tid / kSW) * kRB;
+    float bd[3][kRB];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const float *D = s_in + q * kDW * kDW;
+      for (int task = tid; task < kDW * (kSW / kF2); task += kBlock) {
+        const int r = task / (kSW / kF2), c0 = (task - r * (kSW / kF2)) * kF2;
+        float win[kF2 + kWin - 1];
+#pragma unroll
+        for (int k = 0; k < kF2 + kWin - 1; ++k) win[k] = D[r * kDW + c0 + k];
+#pragma unroll
+        for (int o = 0; o < kF2; ++o) {
+          float acc = 0.f;
+#pragma unroll
+          for (int k = 0; k < kWin; ++k) acc = fmaf(c_win[k], win[o + k], acc);
+          s_h[r * kSW + c0 + o] = acc;
+        }
+      }
+      __syncthreads();
+      float win[kRB + kWin - 1];
+#pragma unroll
+      for (int k = 0; k < kRB + kWin - 1; ++k) win[k] = s_h[(r0 + k) * kSW + c];
+#pragma unroll
+      for (int o = 0; o < kRB; ++o) {
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < kWin; ++k) acc = fmaf(c_win[k], win[o + k], acc);
+        bd[q][o] = acc;
+      }
+      __syncthreads();
+    }
+    const float invN = 1.f / (float)((int64_t)n * h * w);
+#pragma unroll
+    for (int o = 0; o < kRB; ++o) {
+      const int gy = Y0 + r0 + o, gx = X0 + c;
+      if (gx >= w || gy >= h) continue;
+      const int64_t off = ib + (int64_t)gy * w + gx;
+      const float xv = x[off], yv = y[off];
+      const float dssim = bd[0][o] + 2.f * xv * bd[1][o] + yv * bd[2][o];
+      const float d = xv - yv;
+      const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
+      grad[off] = (sg - lambda * dssim) * invN;
+    }
+  }
+  for (int d = kBlock / 2; d > 0; d >>= 1) {
+    if (tid < d) {
+      red[0][tid] += red[0][tid + d];
+      red[1][tid] += red[1][tid + d];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    partials[2 * b] = red[0][0];
+    partials[2 * b + 1] = red[1][0];
+  }
+}
+
+void launch_ssim_fused(const float *x, const float *y, int n, int h, int w, float lambda_ssim,
+                       float *grad, float *partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_ssim_fused, dim3(ssim_num_blocks(n, h, w)), dim3(kBlock), 0, s, x, y, n, h,
+                     w, lambda_ssim, grad, partials);
+}
+
 // Loss and gradient of L1 + lambda D-SSIM (Eq. 8) in one pass that marches
 // down the image.  One wavefront owns a strip of 64 coefficient columns (one
 // per lane: the strip's 54 output columns and a 5-column halo on each side)
@@ -291,16 +479,26 @@ constexpr int kMLanes = 64;               // coefficient columns per strip, one 
 constexpr int kMOut = kMLanes - 2 * kR;   // 54 output columns per strip
 constexpr int kMIn = kMLanes + 2 * kR;    // 74 input columns per strip
 
-// Output rows per segment: the longest of 256, 128, 64, 32 that still gives
-// the launch at least 4096 wavefronts (four per SIMD), or 32.
+// The march serves stacks that give it at least 2048 wavefronts with
+// segments of 64 rows (two per SIMD); its sequential walk down a segment
+// leaves a small stack latency-bound, and those take the tile kernel.
+bool loss_use_march(int n, int h, int w) {
+  return (int64_t)n * ((w + kMOut - 1) / kMOut) * ((h + 63) / 64) >= 2048;
+}
+
+// Output rows per segment: the longest of 256, 128, 64 that still gives the
+// launch at least 4096 wavefronts (four per SIMD), or 64.
 int loss_march_rows(int n, int h, int w) {
   const int64_t strips = (w + kMOut - 1) / kMOut;
   int rows = 256;
-  while (rows > 32 && (int64_t)n * strips * ((h + rows - 1) / rows) < 4096) rows /= 2;
+  while (rows > 64 && (int64_t)n * strips * ((h + rows - 1) / rows) < 4096) rows /= 2;
   return rows;
 }
 
+// Partial-sum pairs of the loss kernel a stack takes (at most one per 32 x 32
+// tile either way).
 int loss_image_blocks(int n, int h, int w) {
+  if (!loss_use_march(n, h, w)) return ssim_num_blocks(n, h, w);
   const int rows = loss_march_rows(n, h, w);
   return n * ((h + rows - 1) / rows) * ((w + kMOut - 1) / kMOut);
 }
@@ -523,6 +721,10 @@ __global__ __launch_bounds__(kMLanes) void k_ssim_march(const float *__restrict_
 
 void launch_ssim_march(const float *x, const float *y, int n, int h, int w, float lambda_ssim,
                        float *grad, float *partials, hipStream_t s) {
+  if (!loss_use_march(n, h, w)) {
+    launch_ssim_fused(x, y, n, h, w, lambda_ssim, grad, partials, s);
+    return;
+  }
   const int rows = loss_march_rows(n, h, w), nb = loss_image_blocks(n, h, w);
   if (grad)
     hipLaunchKernelGGL(k_ssim_march<true>, dim3(nb), dim3(kMLanes), 0, s, x, y, n, h, w, rows,

@@ -344,6 +344,34 @@ def test_image_loss(ops):
     assert np.abs(gg - gref).max() <= 1e-3 * np.abs(gref).max()
 
 
+def test_image_loss_marching_kernel(ops):
+    """A stack just large enough for the marching loss kernel (512 images of
+    65 rows by 55 columns: two 64-row segments by two 54-column strips each,
+    2048 wavefronts, every last segment and strip one pixel wide) against the
+    oracle; on this stack and on a small one (the 32 x 32 tile kernel) the
+    loss without the gradient is bitwise the loss with it."""
+    x = workloads.random_images(13, 512, 65, 55)
+    y = workloads.random_images(14, 512, 65, 55)
+    xt, yt = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    loss, grad = ops.image_loss(xt, yt, ops.Plan(), 0.25)
+    loss0, _ = ops.image_loss(xt, yt, ops.Plan(), 0.25, grad=False)
+    torch.cuda.synchronize()
+    assert torch.equal(loss, loss0)
+    total, l1, s_, gref = oracle.image_loss(x, y, 0.25)
+    lv = loss.cpu().numpy()
+    assert abs(lv[1] - l1) <= 1e-5 * l1 + 1e-7
+    assert abs(lv[2] - s_) <= 2e-5
+    assert abs(lv[0] - total) <= 1e-5 * abs(total) + 1e-6
+    ratio = parity.loss_grad_violation(grad.cpu().numpy(), gref, oracle.image_loss_grad_scale(x, y, 0.25))
+    _report("image loss gradient, marching kernel (per pixel)", ratio)
+    assert ratio <= 1.0
+    xs, ys = xt[:3, :45, :70].contiguous(), yt[:3, :45, :70].contiguous()
+    a, _ = ops.image_loss(xs, ys, ops.Plan(), 0.25)
+    b, _ = ops.image_loss(xs, ys, ops.Plan(), 0.25, grad=False)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
 def test_tv_loss(ops):
     rng = np.random.default_rng(3)
     v = rng.standard_normal((13, 17, 19)).astype(np.float32)

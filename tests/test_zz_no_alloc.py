@@ -38,10 +38,10 @@ def _noalloc(x, y, lam, grad):
 def test_noalloc_loss_matches_plan_loss_on_two_calls():
     torch.cuda.set_device(0)
     plan = ops.Plan()
-    # first call on a larger, ragged stack (several 32 x 32 tiles and a tail),
-    # then a smaller one: the second call's partial sums overwrite only part
-    # of what the first left in the shared buffer
-    for seed, shape in ((3, (5, 300, 277)), (4, (2, 45, 70))):
+    # a stack for the marching loss kernel, then ragged stacks for the tile
+    # kernel, each smaller than the one before: a call's partial sums overwrite
+    # only part of what the earlier ones left in the shared buffer
+    for seed, shape in ((2, (512, 65, 55)), (3, (5, 300, 277)), (4, (2, 45, 70))):
         x, y = _stack(seed, *shape)
         for grad in (True, False):
             ref_loss, ref_g = ops.image_loss(x, y, plan, 0.25, grad=grad)
