@@ -401,8 +401,9 @@ def main():
                          "traffic for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see the sharding notes in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(views would be sharded across GPUs with one all-reduce of the parameter "
+              "gradients; not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
