@@ -299,14 +299,17 @@ def test_binning_and_results_are_bitwise_reproducible(ops):
             assert torch.equal(x, y)
 
 
-def test_wide_detector_binning(ops):
-    """A detector of more than 2048 tiles (1040 x 800: 3250), where the scatter
-    places entries with 32-bit tile masks: two calls give bitwise equal
-    images and gradients, and both match the oracle."""
+@pytest.mark.parametrize("width,height,pitch", [(1040, 800, 0.017), (2048, 1100, 0.0015)])
+def test_wide_detector_binning(ops, width, height, pitch):
+    """Detectors of more than 2048 tiles, where the scatter places entries
+    with 32-bit tile masks: 1040 x 800 (3250 tiles, one window of tiles in
+    LDS) and 2048 x 1100 (8832 tiles, three windows of 4096; the scene covers
+    all three).  Two calls give bitwise equal images and gradients, and both
+    match the oracle."""
     g = scenes.random_scene(46, 2000, lo=0.005, hi=0.05, box=0.9)
-    views = ops.Views.cone([0.7], 13.64, 20.46, 1040, 800, 0.017)
-    ov = [oracle.cone_view(0.7, 13.64, 20.46, 1040, 800, 0.017)]
-    G = upstream(12, (1, 800, 1040))
+    views = ops.Views.cone([0.7], 13.64, 20.46, width, height, pitch)
+    ov = [oracle.cone_view(0.7, 13.64, 20.46, width, height, pitch)]
+    G = upstream(12, (1, height, width))
     t = _dev(g)
     runs = []
     for _ in range(2):
@@ -318,10 +321,10 @@ def test_wide_detector_binning(ops):
     for x, y in zip(runs[0], runs[1]):
         assert torch.equal(x, y)
     v, _ = parity.forward_violation(runs[0][0].cpu().numpy(), oracle.project(g, ov))
-    _report("wide detector forward", v)
+    _report(f"wide detector {width}x{height} forward", v)
     assert v <= 1.0
     el, nr, det = parity.grad_violation(_np(runs[0][1:]), oracle.project_grad(g, ov, G, 3.0, with_scale=True))
-    _report("wide detector gradients", max(el, nr))
+    _report(f"wide detector {width}x{height} gradients", max(el, nr))
     assert el <= 1.0 and nr <= 1.0
 
 
