@@ -643,12 +643,9 @@ def test_c3_training_workload_full_size(ops):
 def test_c3_whole_view_stack(ops):
     """The measured workload's projection on its whole view stack, in the
     launch configuration the benchmark times (200k Gaussians, 75 views of
-    512^2 in one launch): every pixel of all 75 images against the oracle,
-    and the gradients of all 200k Gaussians for an upstream gradient on
-    every pixel in the norm-wise criterion (each block within 1e-3 of the
-    oracle's norm; the per-element criterion, which needs the oracle's
-    per-term magnitudes, is checked on sampled Gaussians above).  The oracle
-    takes about a minute on 16 host threads."""
+    512^2 in one launch): every pixel of all 75 images, and the gradients of
+    all 200k Gaussians for an upstream gradient on every pixel, against the
+    oracle at the stated tolerances (per element and norm-wise)."""
     wl = workloads.c3_iteration()
     views = ops.Views.from_scan(wl.scan)
     t = _dev(wl.gaussians)
@@ -664,15 +661,11 @@ def test_c3_whole_view_stack(ops):
     _report("c3 forward (75 views, every pixel)", v)
     assert v <= 1.0
     print("c3 whole stack: oracle gradients ...", flush=True)
-    rg = oracle.project_grad(wl.gaussians, ov, G, 3.0)
-    gg = _np(grads)
-    worst = 0.0
-    for k in KEYS:
-        nr = float(np.linalg.norm(gg[k].astype(np.float64) - rg[k]) / np.linalg.norm(rg[k]))
-        print(f"c3 whole stack {k}: relative norm error {nr:.3g}", flush=True)
-        worst = max(worst, nr / 1e-3)
-    _report("c3 grads (200k Gaussians, norm-wise)", worst)
-    assert worst <= 1.0
+    rg = oracle.project_grad(wl.gaussians, ov, G, 3.0, with_scale=True)
+    el, nr, det = parity.grad_violation(_np(grads), rg)
+    print(det, flush=True)
+    _report("c3 grads (200k Gaussians)", max(el, nr))
+    assert el <= 1.0 and nr <= 1.0
 
 
 def test_c5_large_sampled(ops):
