@@ -937,10 +937,17 @@ __global__ __launch_bounds__(kBlock) void k_proj_chain(ProjArgs a,
         for (int i = 0; i < 3; ++i)
           gJW[3 * aa + i] = gB[3 * aa] * P.M[3 * i] + gB[3 * aa + 1] * P.M[3 * i + 1] +
                             gB[3 * aa + 2] * P.M[3 * i + 2];
+      // dL/dR = dL/dM S.  The part of S^2 common to the three axes leaves
+      // Sigma = R S^2 R^T unchanged under rotation, so it adds exactly zero
+      // to dL/dq (R^T dR/dq is antisymmetric, dL/dSigma symmetric): it is
+      // left out here, so that a nearly isotropic Gaussian's small rotation
+      // gradient is not the FP32 remainder of a large cancelling sum.  With
+      // dL/dM_ij = 2 (Y R S)_ij, dL/dM_ij (s_j - sbar^2 / s_j) = 2 (Y R (S^2 - sbar^2))_ij.
+      const float sb2 = (G.s[0] * G.s[0] + G.s[1] * G.s[1] + G.s[2] * G.s[2]) * (1.f / 3.f);
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
           const float gM = P.JW[i] * gB[j] + P.JW[3 + i] * gB[3 + j];
-          gR[3 * i + j] += gM * G.s[j];
+          gR[3 * i + j] += gM * (G.s[j] - sb2 * frcp(G.s[j]));
           gs[j] += gM * G.R[3 * i + j];
         }
       // rho_hat = mu rho,  mu = sqrt(2 pi / m),  m = sum_j (r_j / s_j)^2,  r = R^T d
@@ -948,13 +955,21 @@ __global__ __launch_bounds__(kBlock) void k_proj_chain(ProjArgs a,
       // the rectification factor's own dependence on p, s, q (none when unrectified)
       const float gmu = a.rectify ? G.rho * g_rh : 0.f;
       const float gm = gmu * (-0.5f * P.mu / P.m);
+      // m = d^T R S^-2 R^T d: as above, the part of S^-2 common to the
+      // three axes adds nothing to dL/dq and is left out of dL/dR
       float gd[3] = {0.f, 0.f, 0.f};
+      float is1[3], is2[3];
       for (int j = 0; j < 3; ++j) {
-        const float is1 = frcp(G.s[j]), is2 = is1 * is1;
-        const float gr = gm * 2.f * P.r[j] * is2;
-        gs[j] += gm * (-2.f * P.r[j] * P.r[j] * is2 * is1);
+        is1[j] = frcp(G.s[j]);
+        is2[j] = is1[j] * is1[j];
+      }
+      const float ib2 = (is2[0] + is2[1] + is2[2]) * (1.f / 3.f);
+      for (int j = 0; j < 3; ++j) {
+        const float gr = gm * 2.f * P.r[j] * is2[j];
+        const float grR = gm * 2.f * P.r[j] * (is2[j] - ib2);
+        gs[j] += gm * (-2.f * P.r[j] * P.r[j] * is2[j] * is1[j]);
         for (int i = 0; i < 3; ++i) {
-          gR[3 * i + j] += P.d[i] * gr;
+          gR[3 * i + j] += P.d[i] * grR;
           gd[i] += G.R[3 * i + j] * gr;
         }
       }

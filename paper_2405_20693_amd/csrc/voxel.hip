@@ -728,12 +728,18 @@ __global__ __launch_bounds__(kBlock) void k_vox_chain(VoxArgs a,
     // dL/dP (each entry) = -rho/2 Tm;  P = R D R^T, D = diag(s^-2)
     float GP[9];
     for (int i = 0; i < 9; ++i) GP[i] = -0.5f * G.rho * Tm[i];
+    // dL/dR = 2 dL/dP R D.  The part of D common to the three axes leaves P
+    // unchanged under rotation, so it adds exactly zero to dL/dq (R^T dR/dq is
+    // antisymmetric, dL/dP symmetric): it is left out, so that a nearly
+    // isotropic Gaussian's small rotation gradient is not the FP32
+    // remainder of a large cancelling sum
+    const float ib2 = (is2[0] + is2[1] + is2[2]) * (1.f / 3.f);
     float gR[9];
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) {
         float acc = 0.f;
         for (int k = 0; k < 3; ++k) acc += GP[3 * i + k] * G.R[3 * k + j];
-        gR[3 * i + j] = 2.f * acc * is2[j];
+        gR[3 * i + j] = 2.f * acc * (is2[j] - ib2);
       }
     for (int j = 0; j < 3; ++j) {
       float acc = 0.f;
