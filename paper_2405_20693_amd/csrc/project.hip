@@ -584,13 +584,25 @@ void launch_render_fwd(const ProjArgs &a, const Rec2 *rec, const uint2 *list,
 
 constexpr float kChainRange = 120.f;  // exp2 range of the multiplicative walk
 
+// Eight consecutive floats of a 16-B aligned LDS row.
+__device__ inline void load_row8(const float *p, float (&g)[kSub]) {
+  const float4 a = reinterpret_cast<const float4 *>(p)[0], b = reinterpret_cast<const float4 *>(p)[1];
+  g[0] = a.x; g[1] = a.y; g[2] = a.z; g[3] = a.w;
+  g[4] = b.x; g[5] = b.y; g[6] = b.z; g[7] = b.w;
+}
+
 // Same tiling as the forward.  For the upstream gradient G of one tile and
 // each (record, sub-tile) pair that the cutoff keeps, one lane walks the
 // sub-tile's 64 pixels and accumulates the moments
 //   S0 = sum G e, S1 = sum G e dx, S2 = sum G e dy,
 //   S3 = sum G e dx^2, S4 = sum G e dx dy, S5 = sum G e dy^2
 // (pixel units, e = exp2(q'), d = pixel - centre), which determine the
-// gradients with respect to rho_hat, the centre and the conic.  Wave w culls
+// gradients with respect to rho_hat, the centre and the conic.  Down each
+// column the walk keeps three cascaded sums, A += e G, B += A, C += B, one
+// row at a time: after the eight rows A, B and C weight row r by 1, 8 - r and
+// (8 - r)(9 - r)/2, which span 1, Y and Y^2 (Y the row relative to the
+// sub-tile centre), so a pixel costs one FMA and two adds.  The x moments and
+// the shift to the pair's centre follow once per walk.  Wave w culls
 // the batch's records against sub-tile w; the workgroup then walks the kept
 // pairs of all four sub-tiles as one queue in chunks of 64, dealt to the
 // waves in turn, so that lanes stay busy and load is balanced.  Lanes are
@@ -714,15 +726,14 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *_
         const int e = active ? (int)s_q[sw][chain ? pidx : kBlock - 1 - pidx] : 0;
         const int pxl = (sw & 1) * kSub, pyl = (sw >> 1) * kSub;  // the pair's sub-tile
         const float ox = (float)(tx * kTile + pxl), oy = (float)(ty * kTile + pyl);
-        const float *Gsub = s_G + pyl * kTile + pxl;
+        const int goff = pyl * kTile + pxl;
         const float pu = s_pu[e], pv = s_pv[e];
         const float c00 = s_c00[e], c01 = s_c01[e], c11 = s_c11[e];
         const float dx0 = ox - pu, dy0 = oy - pv;
-        // per-column sums over the rows of G e, G e dy, G e dy^2; the x moments
-        // follow from them once per walk (dx is constant down a column)
-        float C0[kSub], C2[kSub], C5[kSub];
+        // per column, the cascaded sums over the rows of e G
+        float A[kSub], B[kSub], C[kSub];
 #pragma unroll
-        for (int col = 0; col < kSub; ++col) C0[col] = C2[col] = C5[col] = 0.f;
+        for (int col = 0; col < kSub; ++col) A[col] = B[col] = C[col] = 0.f;
         if (chain) {
           float e_row = __builtin_amdgcn_exp2f(dx0 * (c00 * dx0 + c01 * dy0) + c11 * dy0 * dy0);
           float rx_row = __builtin_amdgcn_exp2f(c00 * (2.f * dx0 + 1.f) + c01 * dy0);
@@ -732,18 +743,15 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *_
           const float ryy = __builtin_amdgcn_exp2f(2.f * c11);
 #pragma unroll 2
           for (int r = 0; r < kSub; ++r) {
-            const float dy = dy0 + (float)r;
-            const float dy2 = dy * dy;
-            const float4 *Grow = reinterpret_cast<const float4 *>(Gsub + r * kTile);
-            const float4 ga = Grow[0], gb = Grow[1];
-            const float Gr[kSub] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
+            float g[kSub];
+            load_row8(s_G + goff + r * kTile, g);
             float ev = e_row, rx = rx_row;
 #pragma unroll
             for (int col = 0; col < kSub; ++col) {
-              const float ge = (ev >= ethr) ? ev * Gr[col] : 0.f;
-              C0[col] += ge;
-              C2[col] = fmaf(ge, dy, C2[col]);
-              C5[col] = fmaf(ge, dy2, C5[col]);
+              const float se = (ev >= ethr) ? ev : 0.f;
+              A[col] = fmaf(se, g[col], A[col]);
+              B[col] += A[col];
+              C[col] += B[col];
               ev *= rx;
               rx *= rxx;
             }
@@ -757,36 +765,48 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *_
 #pragma unroll 2
           for (int r = 0; r < kSub; ++r) {
             const float dy = oy + (float)r - pv;
-            const float dy2 = dy * dy;
-            float q = dx0 * (c00 * dx0 + c01 * dy) + c11 * dy2;
+            float q = dx0 * (c00 * dx0 + c01 * dy) + c11 * dy * dy;
             float d = c00 * (2.f * dx0 + 1.f) + c01 * dy;
-            const float4 *Grow = reinterpret_cast<const float4 *>(Gsub + r * kTile);
-            const float4 ga = Grow[0], gb = Grow[1];
-            const float Gr[kSub] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
+            float g[kSub];
+            load_row8(s_G + goff + r * kTile, g);
 #pragma unroll
             for (int col = 0; col < kSub; ++col) {
-              const float ex = __builtin_amdgcn_exp2f(q) * Gr[col];
-              const float ge = (q >= thr) ? ex : 0.f;
-              C0[col] += ge;
-              C2[col] = fmaf(ge, dy, C2[col]);
-              C5[col] = fmaf(ge, dy2, C5[col]);
+              const float se = (q >= thr) ? __builtin_amdgcn_exp2f(q) : 0.f;
+              A[col] = fmaf(se, g[col], A[col]);
+              B[col] += A[col];
+              C[col] += B[col];
               q += d;
               d += dd;
             }
           }
         }
-        float S0 = 0.f, S1 = 0.f, S2 = 0.f, S3 = 0.f, S4 = 0.f, S5 = 0.f;
+        // Sums over the columns with weights 1, X, X^2 (X = column - 3.5):
+        // with u = 8 - r = 4.5 - Y, B sums e G u and 2 C - B sums e G u^2, so
+        // sum e G Y = 4.5 A - B and sum e G Y^2 = 20.25 A - 10 B + 2 C.
+        float sA = 0.f, sXA = 0.f, sXXA = 0.f, sB = 0.f, sXB = 0.f, sC = 0.f;
 #pragma unroll
         for (int col = 0; col < kSub; ++col) {
-          const float dx = dx0 + (float)col;
-          S0 += C0[col];
-          const float t1 = C0[col] * dx;
-          S1 += t1;
-          S3 = fmaf(t1, dx, S3);
-          S2 += C2[col];
-          S4 = fmaf(C2[col], dx, S4);
-          S5 += C5[col];
+          const float X = (float)col - 0.5f * (kSub - 1);
+          sA += A[col];
+          sXA = fmaf(X, A[col], sXA);
+          sXXA = fmaf(X * X, A[col], sXXA);
+          sB += B[col];
+          sXB = fmaf(X, B[col], sXB);
+          sC += C[col];
         }
+        // moments about the sub-tile centre (L_ij: weight X^i Y^j) ...
+        const float L00 = sA, L10 = sXA, L20 = sXXA;
+        const float L01 = fmaf(4.5f, sA, -sB);
+        const float L11 = fmaf(4.5f, sXA, -sXB);
+        const float L02 = fmaf(20.25f, sA, fmaf(-10.f, sB, 2.f * sC));
+        // ... shifted to the pair's centre: dx = xc + X, dy = yc + Y
+        const float xc = dx0 + 0.5f * (kSub - 1), yc = dy0 + 0.5f * (kSub - 1);
+        const float S0 = L00;
+        const float S1 = fmaf(xc, L00, L10);
+        const float S2 = fmaf(yc, L00, L01);
+        const float S3 = fmaf(xc, L10 + S1, L20);
+        const float S4 = fmaf(yc, S1, fmaf(xc, L01, L11));
+        const float S5 = fmaf(yc, L01 + S2, L02);
         if (active) {
           s_acc[sw][0][e] = S0; s_acc[sw][1][e] = S1; s_acc[sw][2][e] = S2;
           s_acc[sw][3][e] = S3; s_acc[sw][4][e] = S4; s_acc[sw][5][e] = S5;
