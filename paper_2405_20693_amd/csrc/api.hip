@@ -460,13 +460,13 @@ gs_status proj_bin(gs_plan *pl, const gs_gaussians *g, const gs_view *views, int
       return fail(GS_EHIP, "entry count readback failed");
     GS_TRY(sync_stream(pl, s));
     entries = pl->readback[0];
+    if (entries >= 0xffffffffull || pl->readback[1] >= 0xffffffffull) {
+      (void)clear_running_skipped(pl, 0, s);
+      return fail(GS_EOVERFLOW, "more than 2^32-1 tile entries: split the views over several calls");
+    }
     if (entries != pl->readback[1]) {
       (void)clear_running_skipped(pl, 0, s);
       return fail(GS_EHIP, "internal error: tile and Gaussian entry totals differ");
-    }
-    if (entries >= 0xffffffffull) {
-      (void)clear_running_skipped(pl, 0, s);
-      return fail(GS_EOVERFLOW, "more than 2^32-1 tile entries: split the views over several calls");
     }
     gs_status st = ensure(pl, pl->p_list, 8 * (size_t)entries, s);
     if (st != GS_OK) {
@@ -556,13 +556,13 @@ gs_status vox_bin(gs_plan *pl, const gs_gaussians *g, const gs_grid *grid, float
       return fail(GS_EHIP, "entry count readback failed");
     GS_TRY(sync_stream(pl, s));
     entries = pl->readback[0];
+    if (entries >= 0xffffffffull || pl->readback[1] >= 0xffffffffull) {
+      (void)clear_running_skipped(pl, 1, s);
+      return fail(GS_EOVERFLOW, "more than 2^32-1 voxel tile entries");
+    }
     if (entries != pl->readback[1]) {
       (void)clear_running_skipped(pl, 1, s);
       return fail(GS_EHIP, "internal error: tile and Gaussian entry totals differ");
-    }
-    if (entries >= 0xffffffffull) {
-      (void)clear_running_skipped(pl, 1, s);
-      return fail(GS_EOVERFLOW, "more than 2^32-1 voxel tile entries");
     }
     gs_status st = ensure(pl, pl->v_list, 4 * (size_t)entries, s);
     if (st != GS_OK) {

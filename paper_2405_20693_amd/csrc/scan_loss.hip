@@ -59,11 +59,14 @@ void launch_scan2(const uint32_t *in0, uint32_t *out0, int n0, const uint32_t *i
 
 constexpr int kBigBlock = 4096;  // elements per block of the three-phase scan
 
+// Block sums are formed in 64 bits and stored saturated at 2^32 - 1, so that
+// the total over the blocks reaches 2^32 - 1 whenever the exact total does
+// (the callers reject such totals); below that every block sum is exact.
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t *in, int64_t n,
                                                         uint32_t *block_sums) {
-  __shared__ uint32_t sh[kBlock];
+  __shared__ unsigned long long sh[kBlock];
   const int64_t b = (int64_t)blockIdx.x * kBigBlock;
-  uint32_t s = 0;
+  unsigned long long s = 0;
   for (int i = threadIdx.x; i < kBigBlock; i += kBlock)
     if (b + i < n) s += in[b + i];
   sh[threadIdx.x] = s;
@@ -72,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t *in, int6
     if (threadIdx.x < d) sh[threadIdx.x] += sh[threadIdx.x + d];
     __syncthreads();
   }
-  if (threadIdx.x == 0) block_sums[blockIdx.x] = sh[0];
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = (uint32_t)min(sh[0], 0xffffffffull);
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_top(const uint32_t *in, uint32_t *out,
@@ -109,7 +112,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const uint32_t *in, uint3
   }
 }
 
-// out[0..n) = exclusive scan of in, out[n] = total (32 bits), *total exact.
+// out[0..n) = exclusive scan of in, out[n] = total (32 bits); *total exact
+// below 2^32 - 1 and at least 2^32 - 1 otherwise.
 // block_tmp needs 2 * ceil(n / 4096) + 1 entries.
 void launch_scan_big(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *block_tmp,
                      unsigned long long *total, hipStream_t s) {

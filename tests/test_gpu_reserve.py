@@ -115,6 +115,28 @@ def test_reservation_overflow_is_reported(ops):
         assert torch.equal(a, b)
 
 
+def test_tile_entries_beyond_32_bits_are_refused(ops):
+    """A projection whose binning needs 2^32 - 1 or more tile entries (no
+    cutoff, so every one of 70,000 Gaussians covers all 1,024 tiles of each of
+    64 views of 512^2: 4.59e9 entries) is refused with GS_EOVERFLOW before its
+    scatter runs: the entry totals are summed in 64 bits with saturated block
+    sums, so they cannot wrap to a small count.  The same plan then serves an
+    ordinary call exactly as a fresh plan does."""
+    from paper_2405_20693_amd import _native as N
+    g = scenes.random_scene(61, 70_000, lo=0.02, hi=0.08, box=0.8)
+    t = _dev(g)
+    views = ops.Views.cone(np.linspace(0.0, 2.0 * np.pi, 64, endpoint=False), 13.64, 20.46,
+                           512, 512, 0.035)
+    plan = ops.Plan()
+    with pytest.raises(N.GsError) as e:
+        ops.project_forward(*t, views, float("inf"), plan)
+    assert "GS_EOVERFLOW" in str(e.value)
+    img = ops.project_forward(*t, views, 3.0, plan)
+    ref = ops.project_forward(*t, views, 3.0, ops.Plan())
+    torch.cuda.synchronize()
+    assert torch.equal(img, ref)
+
+
 def test_reserved_plan_refuses_larger_calls(ops):
     g, views, grid = _problem(ops, m=3000)
     t = _dev(g)
