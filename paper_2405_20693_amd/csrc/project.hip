@@ -428,6 +428,12 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
   for (int y = 0; y < kSub; ++y) acc[y] = 0.f;
   // the next batch's entries are loaded while this batch renders
   // the queues' first n records, dealt to the eight groups in turn
+  // The cutoff |e| >= et as a 0/1 factor in one clamped FMA:
+  // m = clamp(|e| S - et' S, 0, 1), et' the float below et and S = 2^(24 - E)
+  // for et in [2^E, 2^(E+1)).  S is a power of two, so |e| S and et' S are
+  // exact, and et - et' >= 2^(E - 24) puts every |e| >= et at or above 1 and
+  // every |e| <= et' at or below 0: m is exactly 1 or 0, and acc + m e is the
+  // same sum as with the comparison.
   auto chain_pass = [&](int n) {
     for (int r = grp; r < n; r += 8) {
       const float4 a0 = s_k[w][0][r], a1 = s_k[w][1][r];
@@ -435,10 +441,11 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
       const float d0 = fmaf(a1.x, lx, a0.w);
       float e = copysignf(__builtin_amdgcn_exp2f(q0), a1.z);
       float rr = __builtin_amdgcn_exp2f(d0);
-      const float et = fabsf(a1.z), R = a1.y;
+      const float S = fabsf(a1.z), cS = a1.w, R = a1.y;
 #pragma unroll
       for (int y = 0; y < kSub; ++y) {
-        acc[y] += (fabsf(e) >= et) ? e : 0.f;
+        const float m = __builtin_amdgcn_fmed3f(fmaf(fabsf(e), S, cS), 0.f, 1.f);
+        acc[y] = fmaf(m, e, acc[y]);
         e *= rr;
         rr *= R;
       }
@@ -503,9 +510,15 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
         const float P = fmaf(hs * hs, c00 + c11, K0);
         const float ea = hs * (K1 + K2), eb = hs * (K1 - K2), ec = hs * hs * c01;
         const float qmin = P + fminf(ec - fabsf(ea), -ec - fabsf(eb));
-        chain = qmin >= r2.y;
+        // the cutoff factor's scale S and offset -et' S (et = 0: no cutoff,
+        // m = 1); thresholds under 2^-100 keep the per-pixel path
+        const float et = fabsf(r1.w);
+        const uint32_t etb = __float_as_uint(et) >> 23;  // biased exponent
+        const float S = et > 0.f ? __uint_as_float((278u - etb) << 23) : 0.f;
+        const float cS = et > 0.f ? -__uint_as_float(__float_as_uint(et) - 1u) * S : 1.f;
+        chain = qmin >= r2.y && (et == 0.f || etb >= 27u);
         k0 = make_float4(A0, A1, c00, B0);
-        k1 = chain ? make_float4(c01, r1.z, r1.w, 0.f)
+        k1 = chain ? make_float4(c01, r1.z, copysignf(S, r1.w), cS)
                    : make_float4(c01, 2.f * c11, r2.x, copysignf(1.f, r1.w));
       }
       // compact: multiplicative records from the front, the others from the back
