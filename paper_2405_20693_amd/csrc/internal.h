@@ -352,6 +352,16 @@ __device__ inline int entry_owner(const uint32_t *off, uint32_t e) {
   return j;
 }
 
+// The same search, for an entry known to belong to one of lo .. hi
+// (hi - lo < 64): off[lo] <= e < off[hi + 1].
+__device__ inline int entry_owner_in(const uint32_t *off, uint32_t e, int lo, int hi) {
+  int j = lo;
+#pragma unroll
+  for (int step = 32; step > 0; step >>= 1)
+    if (j + step <= hi && off[j + step] <= e) j += step;
+  return j;
+}
+
 // ------------------------------------------------------------ launchers --
 
 // Gaussian set of one view of a multi-model projection call (views of one

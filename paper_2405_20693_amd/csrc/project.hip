@@ -226,6 +226,7 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
   __shared__ float s_w[kBlock];           // rectangle width in tiles
   __shared__ float s_pu[kBlock], s_pv[kBlock], s_fa[kBlock], s_fb[kBlock], s_fc[kBlock];
   __shared__ float s_ia[kBlock], s_ic[kBlock];
+  __shared__ int s_jnext;                 // owner of the round's last entry
   const int c = blockIdx.x, v = blockIdx.y, tid = threadIdx.x;
   const int Tw = min(a.T, kScatterWindow);
   MaskT *s_mask = reinterpret_cast<MaskT *>(s_dyn);
@@ -279,18 +280,26 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
       s_ia[tid] = -0.5f * frcp(r.c00);
       s_ic[tid] = -0.5f * frcp(r.c11);
       __syncthreads();
+      // jA: a Gaussian at or below the owner of the round's first entry
+      // (uniform).  The round ends at r1 <= s_off[jA + kRoundG], so its
+      // entries belong to jA .. jA + kRoundG - 1 and the bit j - jA fits the
+      // mask; the next round starts at jA + kRoundG if that bound ended this
+      // one, else at the owner of this round's last entry.
+      int jA = 0;
       for (uint32_t r0 = 0; r0 < total;) {
-        const int jA = entry_owner(s_off, r0);  // first Gaussian of the round (uniform)
-        const uint32_t r1 = min(r0 + (uint32_t)kBlock, s_off[min(jA + kRoundG, kBlock)]);
+        const int jE = min(jA + kRoundG, kBlock);
+        const uint32_t rG = s_off[jE];
+        const uint32_t r1 = min(r0 + (uint32_t)kBlock, rG);
         const uint32_t e = r0 + (uint32_t)tid;
         int t = 0, bit = 0;
         bool act = false;
         uint2 ent;
         if (e < r1) {
-          const int j = entry_owner(s_off, e);
+          const int j = entry_owner_in(s_off, e, jA, jE - 1);
+          if (e + 1 == r1) s_jnext = j;
           const uint32_t kin = e - s_off[j];
           const float wf = s_w[j];
-          int ry = (int)__fdividef((float)kin, wf);  // row within the rectangle, corrected below
+          int ry = (int)((float)kin * frcp(wf));  // row within the rectangle, corrected below
           const int wi = (int)wf;
           if ((uint32_t)((ry + 1) * wi) <= kin) ++ry;
           if ((uint32_t)(ry * wi) > kin) --ry;
@@ -317,6 +326,9 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
           }
         }
         __syncthreads();
+        // read between the round's first and last barriers: the next round
+        // writes s_jnext only after the last one
+        const int jn = s_jnext;
         MaskT mk = 0;
         if (act) {
           mk = s_mask[t];
@@ -329,6 +341,7 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
           s_mask[t] = 0;
         }
         __syncthreads();
+        jA = r1 == rG ? jE : jn;
         r0 = r1;
       }
       base += total;
