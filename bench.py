@@ -180,6 +180,8 @@ def serving_measure(n_requests, fracs, models=None):
         models = [[torch.from_numpy(a).to(dev) for a in (m.mean, m.scale, m.quat, m.density)]
                   for m in workloads.c4_models()]
     servers = {"continuous": ops.Server(n_workers=4, batching=True, max_batch_views=64),
+               "continuous_graphs": ops.Server(n_workers=4, batching=True, max_batch_views=64,
+                                               graphs=True),
                "per_request": ops.Server(n_workers=1, batching=False)}
     for srv in servers.values():
         for m in models:
@@ -234,6 +236,9 @@ def serving_measure(n_requests, fracs, models=None):
                    "20% 128^3 sub-volumes of a 256^3 grid",
             "continuous": "4 workers (streams), 2 batches in flight each, projections of one model "
                           "size class merged across models up to 64 views per launch",
+            "continuous_graphs": "the same batches, each replaying the HIP graph captured for its "
+                                 "shape (views padded to a power of two, detector, size class) "
+                                 "with its views and Gaussian sets copied to device memory first",
             "per_request": "1 worker, one request per launch"}
 
 

@@ -23,6 +23,16 @@
  * request.  A request's result equals the same request run alone up to the
  * FP32 order of partial sums (a batch may split tile lists differently).
  *
+ * Graph replay (batching = 2): continuous batching in which a projection
+ * batch replays a HIP graph captured, when the run starts, for its shape
+ * (views padded to a power of two, detector size, model size class: models
+ * whose binning chunk counts share a power of two).  The batch's request
+ * state, its views and each view's Gaussian set, is copied to device memory
+ * before the replay; the graph's kernels read it there, and its results are
+ * copied to the requests' outputs after it.  Volume queries are launched
+ * directly.  Results equal those of batching = 1 up to the FP32 order of
+ * partial sums.
+ *
  * Per request (batching = 0): the plain path, one request per launch on an
  * allocating plan, waited for, with admission while the estimated memory of
  * the work in flight stays within hbm_budget_bytes.
@@ -44,7 +54,8 @@ typedef struct gs_server gs_server;
 
 typedef struct {
   int32_t n_workers;         /* >= 1 (threads, each with a stream and a plan) */
-  int32_t batching;          /* 0: plain, one request per launch; 1: continuous batching */
+  int32_t batching;          /* 0: plain, one request per launch; 1: continuous batching;
+                                2: continuous batching with graph replay */
   int32_t max_batch_views;   /* >= 1, views per merged projection launch */
   float cutoff;              /* Mahalanobis cutoff of every request (> 0, INFINITY = none) */
   int64_t hbm_budget_bytes;  /* > 0: device memory of the workers' workspaces (continuous)

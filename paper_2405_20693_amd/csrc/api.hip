@@ -364,33 +364,17 @@ bool same_vox(const gs_plan *pl, const gs_gaussians *g, const gs_grid *grid, flo
          std::memcmp(&k.grid, grid, sizeof(gs_grid)) == 0;
 }
 
-// Projection + binning: records, tile lists and backward slot offsets.
-// models/view_model: NULL for a single-model call on g; else view v renders
-// models[view_model[v]] (g is then models[view_model[0]]).
-gs_status proj_bin(gs_plan *pl, const gs_gaussians *g, const gs_view *views, int32_t nv,
-                   float cutoff, hipStream_t s, const gs_gaussians *models = nullptr,
-                   const int32_t *view_model = nullptr) {
-  pl->p_valid = false;
-  ProjArgs a{};
-  a.mean = g->mean; a.scale = g->scale; a.quat = g->quat; a.dens = g->density;
-  a.M = g->n;
+// Kernel arguments of a projection of nv views of width x height with at
+// most M Gaussians per view and R records in all: tiles, binning chunks,
+// render parts and the cutoff constants (no buffers yet).
+gs_status proj_args(const gs_plan *pl, int32_t nv, int32_t width, int32_t height, int64_t M,
+                    int64_t R, float cutoff, ProjArgs &a) {
+  a = ProjArgs{};
+  a.M = M;
+  a.R = R;
   a.V = nv;
-  std::vector<ViewSet> sets;
-  if (models) {
-    sets.resize((size_t)nv);
-    int64_t r = 0;
-    for (int v = 0; v < nv; ++v) {
-      const gs_gaussians &m = models[view_model[v]];
-      sets[(size_t)v] = ViewSet{m.mean, m.scale, m.quat, m.density, m.n, r};
-      r += m.n;
-      a.M = std::max<int64_t>(a.M, m.n);
-    }
-    a.R = r;
-  } else {
-    a.R = (int64_t)nv * a.M;
-  }
-  a.width = views[0].width;
-  a.height = views[0].height;
+  a.width = width;
+  a.height = height;
   a.TX = (a.width + kTile - 1) / kTile;
   a.TY = (a.height + kTile - 1) / kTile;
   a.T = a.TX * a.TY;
@@ -412,12 +396,17 @@ gs_status proj_bin(gs_plan *pl, const gs_gaussians *g, const gs_view *views, int
   cutoff_consts(cutoff, a.kappa, a.thr, a.qmax);
   a.rectify = pl->rectify;
   a.ovf_host = pl->reserved ? pl->ovf_flag_dev : nullptr;
-  const int64_t VM = a.R, VT = (int64_t)nv * a.T, VC = (int64_t)nv * a.C;
-  if (VT + 1 > 0x7fffffffLL || VC + 1 > 0x7fffffffLL)
+  if ((int64_t)nv * a.T + 1 > 0x7fffffffLL || (int64_t)nv * a.C + 1 > 0x7fffffffLL)
     return fail(GS_EUNSUPPORTED, "too many views in one call");
-  GS_TRY(upload_views(pl, views, nv, s, models ? sets.data() : nullptr));
-  a.views = P<DevView>(pl->p_views);
-  a.sets = models ? reinterpret_cast<const ViewSet *>(P<DevView>(pl->p_views) + nv) : nullptr;
+  return GS_OK;
+}
+
+// The binning of arguments a whose views (and sets) are on the device:
+// records, tile histograms and scans, the entry count (read back unless the
+// plan is reserved) and the scatter into tile lists and slot offsets.
+gs_status proj_bin_launch(gs_plan *pl, ProjArgs &a, hipStream_t s) {
+  const int nv = a.V;
+  const int64_t VM = a.R, VT = (int64_t)nv * a.T, VC = (int64_t)nv * a.C;
   GS_TRY(ensure(pl, pl->p_rec, sizeof(Rec2) * VM, s));
   GS_TRY(ensure(pl, pl->p_hist, 4 * VC * a.T, s));
   GS_TRY(ensure(pl, pl->p_tile_total, 4 * VT, s));
@@ -482,8 +471,38 @@ gs_status proj_bin(gs_plan *pl, const gs_gaussians *g, const gs_view *views, int
                       P<unsigned long long>(pl->p_totals), s);
   t_sc.stop();
   GS_TRY(check_launch("projection scatter"));
-  pl->pargs = a;
   pl->p_entries = entries;
+  return GS_OK;
+}
+
+// Projection + binning: records, tile lists and backward slot offsets.
+// models/view_model: NULL for a single-model call on g; else view v renders
+// models[view_model[v]] (g is then models[view_model[0]]).
+gs_status proj_bin(gs_plan *pl, const gs_gaussians *g, const gs_view *views, int32_t nv,
+                   float cutoff, hipStream_t s, const gs_gaussians *models = nullptr,
+                   const int32_t *view_model = nullptr) {
+  pl->p_valid = false;
+  int64_t M = g->n, R = 0;
+  std::vector<ViewSet> sets;
+  if (models) {
+    sets.resize((size_t)nv);
+    for (int v = 0; v < nv; ++v) {
+      const gs_gaussians &m = models[view_model[v]];
+      sets[(size_t)v] = ViewSet{m.mean, m.scale, m.quat, m.density, m.n, R};
+      R += m.n;
+      M = std::max<int64_t>(M, m.n);
+    }
+  } else {
+    R = (int64_t)nv * M;
+  }
+  ProjArgs a;
+  GS_TRY(proj_args(pl, nv, views[0].width, views[0].height, M, R, cutoff, a));
+  a.mean = g->mean; a.scale = g->scale; a.quat = g->quat; a.dens = g->density;
+  GS_TRY(upload_views(pl, views, nv, s, models ? sets.data() : nullptr));
+  a.views = P<DevView>(pl->p_views);
+  a.sets = models ? reinterpret_cast<const ViewSet *>(P<DevView>(pl->p_views) + nv) : nullptr;
+  GS_TRY(proj_bin_launch(pl, a, s));
+  pl->pargs = a;
   pl->pkey.mean = g->mean; pl->pkey.scale = g->scale; pl->pkey.quat = g->quat;
   pl->pkey.dens = g->density; pl->pkey.n = g->n; pl->pkey.cutoff = cutoff;
   pl->pkey.views.assign(views, views + nv);
@@ -1305,6 +1324,38 @@ const unsigned long long *plan_entries_needed(const gs_plan *p, int voxel) {
 int64_t plan_entry_capacity(const gs_plan *p, int voxel) {
   if (!p || !p->reserved) return 0;
   return (int64_t)(voxel ? p->v_list.cap / 4 : p->p_list.cap / 8);
+}
+
+DevView dev_view(const gs_view &v) { return make_dev_view(v); }
+
+gs_status project_fwd_device(gs_plan *pl, const DevView *views, const ViewSet *sets, int32_t nv,
+                             int32_t width, int32_t height, int64_t M_bound, int64_t R_bound,
+                             float cutoff, float *image, hipStream_t s) {
+  if (!pl || !pl->reserved) return fail(GS_EINVAL, "a reserved plan is required");
+  if (!views || !sets || !image || nv < 1 || M_bound < 1 || R_bound < 1)
+    return fail(GS_EINVAL, "invalid device projection arguments");
+  GS_TRY(check_cutoff(cutoff));
+  if (pl->timing) return fail(GS_EINVAL, "stage timing is not available on this path");
+  GS_TRY(reserved_overflow(pl));
+  pl->used = true;
+  pl->last_stream = s;
+  pl->p_valid = false;  // a multi-model binning serves no backward
+  ProjArgs a;
+  GS_TRY(proj_args(pl, nv, width, height, M_bound, R_bound, cutoff, a));
+  // the forward's kernels read each view's Gaussians from its set; the
+  // single-model pointers stay null
+  a.views = views;
+  a.sets = sets;
+  GS_TRY(proj_bin_launch(pl, a, s));
+  pl->pargs = a;
+  float *partial = nullptr;
+  if (a.parts > 1) {
+    GS_TRY(ensure(pl, pl->p_fpart, 4 * (size_t)a.parts * (size_t)a.V * a.T * kBlock, s));
+    partial = P<float>(pl->p_fpart);
+  }
+  launch_render_fwd(a, P<Rec2>(pl->p_rec), P<uint2>(pl->p_list), P<uint32_t>(pl->p_tile_start),
+                    image, partial, s);
+  return check_launch("render forward");
 }
 
 gs_status adam_step_guarded(const gs_params *p, int64_t n, const gs_grads *grads,

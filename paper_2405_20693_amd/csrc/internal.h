@@ -503,6 +503,20 @@ const unsigned long long *plan_control_words(const gs_plan *p);
 // entries a reserved plan holds for that operator (0 if not reserved).
 const unsigned long long *plan_entries_needed(const gs_plan *p, int voxel);
 int64_t plan_entry_capacity(const gs_plan *p, int voxel);
+// The device form of a view.
+DevView dev_view(const gs_view &v);
+// Forward projection of several models' views on a reserved plan, issuing
+// kernel launches only (no copy, memset, event or host synchronization), so
+// that a graph captured from it can be replayed for other batches of the same
+// shape: the views (DevView[nv]) and per-view Gaussian sets (ViewSet[nv],
+// records of view v from sets[v].rbase) are read from device memory, and the
+// launch is sized for at most M_bound Gaussians per view and R_bound records,
+// so its arguments depend on (nv, detector, bounds, cutoff, image) alone.
+// Views beyond a batch's own may carry empty sets (n = 0).  Stage timing must
+// be off on the plan.
+gs_status project_fwd_device(gs_plan *pl, const DevView *views, const ViewSet *sets, int32_t nv,
+                             int32_t width, int32_t height, int64_t M_bound, int64_t R_bound,
+                             float cutoff, float *image, hipStream_t s);
 // gs_adam_step that does nothing on the device when plan g0 or g1 (either may
 // be null) records a call that overflowed its reservation since its last check.
 gs_status adam_step_guarded(const gs_params *p, int64_t n, const gs_grads *grads,

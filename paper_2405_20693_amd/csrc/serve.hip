@@ -17,6 +17,17 @@
 // needed and its requests are served again one by one; a request that
 // overflows alone fails with GS_ENOMEM.
 //
+// Graph replay (batching = 2): as continuous batching, but a projection
+// batch replays a HIP graph captured, when the run starts, for its shape:
+// views padded to a power of two (at most the reservation's views), detector
+// size, and model size class (the launch is sized for the largest model of
+// the class).  The batch's request state, its views and the Gaussian set of
+// each view (padding views get empty sets), is written to pinned host memory
+// of the batch's slot and copied to the worker's device buffer before the
+// replay; the graph renders into the worker's image buffer, and the results
+// are copied to the requests' outputs after it, all on the worker's stream.
+// Volume queries are launched directly.
+//
 // Per request (batching = 0): the plain path, one request per launch on an
 // allocating plan, the stream synchronized after each.
 #include <algorithm>
@@ -62,6 +73,14 @@ struct Worker {
   std::deque<Batch> inflight;
   std::vector<gs_view> views;
   std::vector<int32_t> view_model;
+  // graph replay: per slot the batch's DevView[lim.views] then
+  // ViewSet[lim.views] in pinned memory, their device copy, the image buffer
+  // of the replays, and the executable graph of each batch shape
+  // (views, width, height, size class)
+  void *vs_host[kInflight] = {};
+  void *vs_dev = nullptr;
+  float *img_dev = nullptr;
+  std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;
   // plain path
   float *scratch = nullptr;
   size_t scratch_cap = 0;  // floats
@@ -70,6 +89,7 @@ struct Worker {
 // Limits of one worker's reservation.
 struct Limits {
   int32_t views = 0, width = 0, height = 0;
+  int64_t m_max = 0;  // the largest model
   int64_t records = 0, proj_entries = 0, vox_entries = 0, voxels = 0, slot_floats = 0;
   int32_t nx = 0, ny = 0, nz = 0;
 };
@@ -261,6 +281,19 @@ int size_class(int64_t m) {
   return c;
 }
 
+// The largest model of size class c (2^(c+1) - 1 chunks), at most m_max.
+int64_t class_bound(int c, int64_t m_max) {
+  return std::min<int64_t>(m_max, 4096 * ((int64_t{2} << c) - 1));
+}
+
+// Views of a graph for a batch of nv views: the next power of two, at most
+// the reservation's views.
+int32_t graph_views(int32_t nv, int32_t lim_views) {
+  int32_t nb = 1;
+  while (nb < nv) nb *= 2;
+  return std::min(nb, lim_views);
+}
+
 // Takes the next batch from the queue (lock held): the oldest request and,
 // for a projection, later queued projections of the same detector size while
 // the views, records, entries and output slot stay within the reservation.
@@ -308,8 +341,92 @@ bool take_batch(gs_server *s, Batch &b) {
   return false;
 }
 
+// Captures the worker's graph for batches of nb views of one detector size
+// and size class (the stream must have no capture in progress).
+gs_status capture_graph(gs_server *s, Worker &w, int32_t nb, int32_t width, int32_t height, int cls,
+                        hipGraphExec_t *exec) {
+  const Limits &L = s->lim;
+  const gsk::DevView *dv = static_cast<const gsk::DevView *>(w.vs_dev);
+  const gsk::ViewSet *ds = reinterpret_cast<const gsk::ViewSet *>(dv + L.views);
+  if (hipStreamBeginCapture(w.stream, hipStreamCaptureModeRelaxed) != hipSuccess)
+    return err(GS_EHIP, "hipStreamBeginCapture failed");
+  gs_status st = gsk::project_fwd_device(w.plan, dv, ds, nb, width, height,
+                                         class_bound(cls, L.m_max), L.records, s->cfg.cutoff,
+                                         w.img_dev, w.stream);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(w.stream, &graph);
+  if (st != GS_OK || e != hipSuccess || !graph) {
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    return st != GS_OK ? st : err(GS_EHIP, "hipStreamEndCapture failed");
+  }
+  const hipError_t ie = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) {
+    (void)hipGetLastError();
+    return err(GS_EHIP, "hipGraphInstantiate failed");
+  }
+  return GS_OK;
+}
+
+// A projection batch by graph replay: its views and sets to the device, the
+// graph of its shape, its results to the requests' outputs.
+gs_status submit_graph(gs_server *s, Worker &w, Batch &b) {
+  const Limits &L = s->lim;
+  const gs_request &head = s->reqs[b.reqs[0]];
+  const int32_t width = head.views[0].width, height = head.views[0].height;
+  b.cap = gsk::plan_entry_capacity(w.plan, 0);
+  gsk::DevView *hv = static_cast<gsk::DevView *>(w.vs_host[b.slot]);
+  gsk::ViewSet *hs = reinterpret_cast<gsk::ViewSet *>(hv + L.views);
+  int32_t nv = 0;
+  int64_t rb = 0;
+  for (int64_t i : b.reqs) {
+    const gs_request &r = s->reqs[i];
+    const gs_gaussians &m = s->models[r.model];
+    for (int32_t k = 0; k < r.n_views; ++k, ++nv) {
+      hv[nv] = gsk::dev_view(r.views[k]);
+      hs[nv] = gsk::ViewSet{m.mean, m.scale, m.quat, m.density, m.n, rb};
+      rb += m.n;
+    }
+  }
+  const int32_t nb = graph_views(nv, L.views);
+  for (int32_t v = nv; v < nb; ++v) {
+    hv[v] = hv[0];
+    hs[v] = gsk::ViewSet{hs[0].mean, hs[0].scale, hs[0].quat, hs[0].dens, 0, rb};
+  }
+  const size_t bytes = (sizeof(gsk::DevView) + sizeof(gsk::ViewSet)) * (size_t)L.views;
+  if (hipMemcpyAsync(w.vs_dev, w.vs_host[b.slot], bytes, hipMemcpyHostToDevice, w.stream) !=
+      hipSuccess)
+    return GS_EHIP;
+  const int cls = size_class(s->models[head.model].n);
+  const auto key = std::make_tuple((int)nb, (int)width, (int)height, cls);
+  auto it = w.graphs.find(key);
+  if (it == w.graphs.end()) {  // a shape the run did not foresee
+    hipGraphExec_t exec = nullptr;
+    const gs_status st = capture_graph(s, w, nb, width, height, cls, &exec);
+    if (st != GS_OK) return st;
+    it = w.graphs.emplace(key, exec).first;
+  }
+  if (hipGraphLaunch(it->second, w.stream) != hipSuccess) return GS_EHIP;
+  if (hipMemcpyAsync(&w.need[b.slot], gsk::plan_entries_needed(w.plan, 0), 8,
+                     hipMemcpyDeviceToHost, w.stream) != hipSuccess)
+    return GS_EHIP;
+  const size_t img = (size_t)width * height;
+  size_t off = 0;
+  for (int64_t i : b.reqs) {
+    const gs_request &r = s->reqs[i];
+    const size_t n = img * (size_t)r.n_views;
+    if (r.out && hipMemcpyAsync(r.out, w.img_dev + off, n * sizeof(float), hipMemcpyDeviceToDevice,
+                                w.stream) != hipSuccess)
+      return GS_EHIP;
+    off += n;
+  }
+  return hipEventRecord(b.done, w.stream) == hipSuccess ? GS_OK : GS_EHIP;
+}
+
 // Enqueues a batch on the worker's stream without waiting for it.
 gs_status submit(gs_server *s, Worker &w, Batch &b) {
+  if (b.kind == GS_REQ_PROJECT && s->cfg.batching == 2) return submit_graph(s, w, b);
   float *out = w.slot_buf[b.slot];
   const gs_request &head = s->reqs[b.reqs[0]];
   gs_status st;
@@ -501,8 +618,67 @@ void release_workers(gs_server *s) {
       if (b) (void)hipFree(b);
       b = nullptr;
     }
+    for (auto &g : w.graphs) (void)hipGraphExecDestroy(g.second);
+    w.graphs.clear();
+    for (auto &h : w.vs_host) {
+      if (h) (void)hipHostFree(h);
+      h = nullptr;
+    }
+    if (w.vs_dev) (void)hipFree(w.vs_dev);
+    if (w.img_dev) (void)hipFree(w.img_dev);
+    w.vs_dev = nullptr;
+    w.img_dev = nullptr;
   }
   s->reserved_bytes = 0;
+}
+
+// Graph replay: each worker's request-state buffers and image buffer, and
+// its graphs for every batch shape the trace can produce (views padded to
+// powers of two up to the reservation's, the trace's detector sizes and the
+// size classes of its projected models), captured before the run starts.
+gs_status prepare_graphs(gs_server *s, const gs_request *reqs, int64_t n) {
+  const Limits &L = s->lim;
+  if (L.views < 1) return GS_OK;
+  std::vector<std::pair<int, int>> sizes;
+  std::vector<int> classes;
+  for (int64_t i = 0; i < n; ++i) {
+    const gs_request &r = reqs[i];
+    if (r.kind != GS_REQ_PROJECT) continue;
+    const std::pair<int, int> wh(r.views[0].width, r.views[0].height);
+    if (std::find(sizes.begin(), sizes.end(), wh) == sizes.end()) sizes.push_back(wh);
+    const int c = size_class(s->models[r.model].n);
+    if (std::find(classes.begin(), classes.end(), c) == classes.end()) classes.push_back(c);
+  }
+  std::vector<int32_t> counts;
+  for (int32_t nb = 1;; nb *= 2) {
+    counts.push_back(std::min(nb, L.views));
+    if (nb >= L.views) break;
+  }
+  const size_t vs_bytes = (sizeof(gsk::DevView) + sizeof(gsk::ViewSet)) * (size_t)L.views;
+  const size_t img_floats = (size_t)L.views * L.width * L.height;
+  for (auto &w : s->workers) {
+    if (hipMalloc(&w.vs_dev, vs_bytes) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&w.img_dev), sizeof(float) * img_floats) != hipSuccess) {
+      (void)hipGetLastError();
+      return err(GS_ENOMEM, "serving graph buffers allocation failed");
+    }
+    for (auto &h : w.vs_host)
+      if (hipHostMalloc(&h, vs_bytes, hipHostMallocDefault) != hipSuccess) {
+        h = nullptr;
+        return err(GS_ENOMEM, "serving pinned request state allocation failed");
+      }
+    for (const auto &wh : sizes)
+      for (int c : classes)
+        for (int32_t nb : counts) {
+          const auto key = std::make_tuple((int)nb, wh.first, wh.second, c);
+          if (w.graphs.count(key)) continue;
+          hipGraphExec_t exec = nullptr;
+          const gs_status st = capture_graph(s, w, nb, wh.first, wh.second, c, &exec);
+          if (st != GS_OK) return st;
+          w.graphs.emplace(key, exec);
+        }
+  }
+  return GS_OK;
 }
 
 // Sizes and reserves every worker's plan and output slots for the trace
@@ -540,6 +716,7 @@ gs_status reserve_workers(gs_server *s, const gs_request *reqs, int64_t n) {
       L.views = views;
       if (views == 0) L.width = L.height = 0;
       L.records = (int64_t)views * m_max;
+      L.m_max = m_max;
       L.proj_entries = std::min<int64_t>((int64_t)views * view_need, 0xfffffffeLL);
       L.vox_entries = with_vol ? std::min<int64_t>(vol_need_max, 0xfffffffeLL) : 0;
       L.slot_floats = std::max<int64_t>((int64_t)views * L.width * L.height, L.voxels);
@@ -559,6 +736,9 @@ gs_status reserve_workers(gs_server *s, const gs_request *reqs, int64_t n) {
       gs_status st = gs_plan_reserve_bytes(&r, &bytes);
       if (st != GS_OK) return st;
       bytes += (int64_t)kInflight * L.slot_floats * (int64_t)sizeof(float);
+      if (s->cfg.batching == 2)  // the replays' image buffer and request state
+        bytes += (int64_t)L.views * L.width * L.height * (int64_t)sizeof(float) +
+                 (int64_t)(sizeof(gsk::DevView) + sizeof(gsk::ViewSet)) * L.views;
       if (bytes <= share && (views > 0 || with_vol)) {
         for (auto &w : s->workers) {
           st = gs_plan_reserve(w.plan, &r, w.stream);
@@ -591,6 +771,7 @@ gs_status gs_server_create(const gs_server_config *cfg, gs_server **out) {
   if (!cfg || !out) return GS_EINVAL;
   *out = nullptr;
   if (cfg->n_workers < 1 || cfg->n_workers > 64 || cfg->max_batch_views < 1 ||
+      cfg->batching < 0 || cfg->batching > 2 ||
       !(cfg->cutoff > 0.f) || cfg->hbm_budget_bytes <= 0)
     return GS_EINVAL;
   gs_server *s = new (std::nothrow) gs_server();
@@ -659,6 +840,7 @@ gs_status gs_server_run(gs_server *s, const gs_request *reqs, int64_t n, double 
     release_workers(s);
     gs_status st = measure_entries(s, reqs, n, s->workers[0].stream);
     if (st == GS_OK) st = reserve_workers(s, reqs, n);
+    if (st == GS_OK && s->cfg.batching == 2) st = prepare_graphs(s, reqs, n);
     if (st != GS_OK) return st;
   }
   std::vector<int64_t> order((size_t)n);

@@ -352,15 +352,17 @@ def voxelize(mean, scale, quat, density, grid, cutoff=3.0, plan=None):
 class Server:
     """Request loop of include/gs_serve.h: worker threads with their own
     streams and plans; continuous batching of projections across models into
-    one launch within reserved workspaces sized from the HBM budget, or the
+    one launch within reserved workspaces sized from the HBM budget (with
+    graphs=True each batch replays a HIP graph captured for its shape), or the
     plain one-request-per-launch path.  All work runs in libgs.so."""
 
     def __init__(self, n_workers=4, batching=True, max_batch_views=128, cutoff=3.0,
-                 hbm_budget_bytes=None):
+                 hbm_budget_bytes=None, graphs=False):
         if hbm_budget_bytes is None:
             free, _ = torch.cuda.mem_get_info()
             hbm_budget_bytes = int(0.25 * free)
-        cfg = N.GsServerConfig(int(n_workers), int(bool(batching)), int(max_batch_views),
+        mode = (2 if graphs else 1) if batching else 0
+        cfg = N.GsServerConfig(int(n_workers), mode, int(max_batch_views),
                                float(cutoff), int(hbm_budget_bytes))
         h = ctypes.c_void_p()
         N.call("gs_server_create", ctypes.byref(cfg), ctypes.byref(h))

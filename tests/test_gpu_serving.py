@@ -78,10 +78,17 @@ def test_multi_model_projection_matches_single_model_calls(ops):
         ops.project_forward_multi(dm, [0, 1, 3, 0, 0, 0, 0], views, 3.0)
 
 
-def test_results_same_alone_and_in_the_mix(ops):
+@pytest.mark.parametrize("graphs", [False, True])
+def test_results_same_alone_and_in_the_mix(ops, graphs):
+    """A mixed trace of projections (two detector sizes, two models) and
+    volume queries, served with continuous batching (directly launched, or by
+    replaying the graph captured for each batch shape): every result equals
+    the same request run alone within the FP32 summation-order tolerance, and
+    sampled results match the oracle."""
     models = [scenes.random_scene(81, 1500, lo=0.02, hi=0.1), scenes.random_scene(82, 900, lo=0.03, hi=0.12)]
     dm = [_dev(m) for m in models]
-    srv = ops.Server(n_workers=3, batching=True, max_batch_views=64, hbm_budget_bytes=1 << 30)
+    srv = ops.Server(n_workers=3, batching=True, max_batch_views=64, hbm_budget_bytes=1 << 30,
+                     graphs=graphs)
     for m in dm:
         srv.add_model(*m)
     reqs = _requests(ops, np.random.default_rng(0), 24)
@@ -123,7 +130,8 @@ def test_admission_refuses_work_above_the_budget(ops):
         srv.run([small, big, small], time_scale=0.0)
 
 
-def test_serving_a_c4_sized_model(ops):
+@pytest.mark.parametrize("graphs", [False, True])
+def test_serving_a_c4_sized_model(ops, graphs):
     """A resident model of the serving workload's size class (220k phantom
     Gaussians) next to two small ones: 512^2 and 256^2 cone projections of 1-8
     views and a 128^3 sub-volume of the 256^3 grid, served in one mixed,
@@ -135,7 +143,8 @@ def test_serving_a_c4_sized_model(ops):
     models = [big, scenes.random_scene(84, 1200, lo=0.02, hi=0.1),
               scenes.random_scene(85, 800, lo=0.03, hi=0.12)]
     dm = [_dev(m) for m in models]
-    srv = ops.Server(n_workers=3, batching=True, max_batch_views=64, hbm_budget_bytes=8 << 30)
+    srv = ops.Server(n_workers=3, batching=True, max_batch_views=64, hbm_budget_bytes=8 << 30,
+                     graphs=graphs)
     for m in dm:
         srv.add_model(*m)
     rng = np.random.default_rng(5)
@@ -183,7 +192,8 @@ def test_serving_a_c4_sized_model(ops):
     assert v <= 1.0
 
 
-def test_continuous_workspace_stays_within_the_budget(ops):
+@pytest.mark.parametrize("graphs", [False, True])
+def test_continuous_workspace_stays_within_the_budget(ops, graphs):
     """Continuous batching reserves each worker's workspace from its share of
     the HBM budget when a run starts: the reservation is at most the budget,
     the device memory the run takes is that reservation, and requests of
@@ -191,7 +201,8 @@ def test_continuous_workspace_stays_within_the_budget(ops):
     models = [scenes.random_scene(90 + k, 600 + 400 * k, lo=0.02, hi=0.1) for k in range(4)]
     dm = [_dev(m) for m in models]
     budget = 96 << 20
-    srv = ops.Server(n_workers=2, batching=True, max_batch_views=32, hbm_budget_bytes=budget)
+    srv = ops.Server(n_workers=2, batching=True, max_batch_views=32, hbm_budget_bytes=budget,
+                     graphs=graphs)
     for m in dm:
         srv.add_model(*m)
     rng = np.random.default_rng(12)
@@ -221,3 +232,40 @@ def test_continuous_workspace_stays_within_the_budget(ops):
         torch.cuda.synchronize()
         a = alone.cpu().numpy()
         assert np.abs(a - r["out"].cpu().numpy()).max() <= 1e-5 * max(float(np.abs(a).max()), 1e-30)
+
+
+def test_graph_replays_across_runs_and_batches(ops):
+    """Graph replay over two runs of one server (the second trace smaller, with
+    the models' densities changed in place in between): the graphs of each run
+    are replayed for many batches of different request state, and every result
+    equals the same request run alone on the current Gaussians."""
+    models = [scenes.random_scene(95, 1300, lo=0.02, hi=0.1), scenes.random_scene(96, 500, lo=0.03, hi=0.12),
+              scenes.random_scene(97, 9000, lo=0.01, hi=0.05)]
+    dm = [_dev(m) for m in models]
+    srv = ops.Server(n_workers=2, batching=True, max_batch_views=16, hbm_budget_bytes=1 << 30,
+                     graphs=True)
+    for m in dm:
+        srv.add_model(*m)
+    rng = np.random.default_rng(21)
+    for n_req, scale in ((48, 1.0), (20, 1.7)):
+        with torch.no_grad():
+            for m in dm:
+                m[3].mul_(scale)
+        reqs = []
+        for i in range(n_req):
+            nv = int(rng.integers(1, 7))
+            th = rng.uniform(0, 6.28) + np.arange(nv) * 6.28 / nv
+            det = (32, 48)[i % 2]
+            reqs.append({"kind": "project", "model": int(rng.integers(0, 3)), "arrival_s": 0.0,
+                         "views": ops.Views.cone(th, 13.64, 20.46, det, det, 0.05),
+                         "out": torch.full((nv, det, det), float("nan"), device="cuda")})
+        res, wall = srv.run(reqs, time_scale=0.0)
+        torch.cuda.synchronize()
+        assert all(r["status"] == 0 for r in res)
+        assert max(r["batch_size"] for r in res) > 1
+        for r in reqs:
+            alone = ops.project_forward(*dm[r["model"]], r["views"], 3.0, ops.Plan())
+            torch.cuda.synchronize()
+            a, b = alone.cpu().numpy(), r["out"].cpu().numpy()
+            assert np.all(np.isfinite(b))
+            assert np.abs(a - b).max() <= 1e-5 * max(float(np.abs(a).max()), 1e-30)
