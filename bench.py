@@ -237,7 +237,7 @@ def serving_measure(n_requests, fracs, models=None):
             "continuous": "4 workers (streams), 2 batches in flight each, projections of one model "
                           "size class merged across models up to 64 views per launch",
             "continuous_graphs": "the same batches, each replaying the HIP graph captured for its "
-                                 "shape (views padded to a power of two, detector, size class) "
+                                 "shape (views padded to a multiple of 8 above 8, detector, size class) "
                                  "with its views and Gaussian sets copied to device memory first",
             "per_request": "1 worker, one request per launch"}
 

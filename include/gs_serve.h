@@ -25,7 +25,7 @@
  *
  * Graph replay (batching = 2): continuous batching in which a projection
  * batch replays a HIP graph captured, when the run starts, for its shape
- * (views padded to a power of two, detector size, model size class: models
+ * (views padded to a multiple of 8 above 8, detector size, model size class: models
  * whose binning chunk counts share a power of two).  The batch's request
  * state, its views and each view's Gaussian set, is copied to device memory
  * before the replay; the graph's kernels read it there, and its results are

@@ -19,8 +19,8 @@
 //
 // Graph replay (batching = 2): as continuous batching, but a projection
 // batch replays a HIP graph captured, when the run starts, for its shape:
-// views padded to a power of two (at most the reservation's views), detector
-// size, and model size class (the launch is sized for the largest model of
+// views (padded to a multiple of 8 above 8, at most the reservation's),
+// detector size, and model size class (the launch is sized for the largest model of
 // the class).  The batch's request state, its views and the Gaussian set of
 // each view (padding views get empty sets), is written to pinned host memory
 // of the batch's slot and copied to the worker's device buffer before the
@@ -286,11 +286,10 @@ int64_t class_bound(int c, int64_t m_max) {
   return std::min<int64_t>(m_max, 4096 * ((int64_t{2} << c) - 1));
 }
 
-// Views of a graph for a batch of nv views: the next power of two, at most
-// the reservation's views.
+// Views of a graph for a batch of nv views: nv up to 8, else the next
+// multiple of 8, at most the reservation's views.
 int32_t graph_views(int32_t nv, int32_t lim_views) {
-  int32_t nb = 1;
-  while (nb < nv) nb *= 2;
+  const int32_t nb = nv <= 8 ? nv : (nv + 7) / 8 * 8;
   return std::min(nb, lim_views);
 }
 
@@ -633,9 +632,9 @@ void release_workers(gs_server *s) {
 }
 
 // Graph replay: each worker's request-state buffers and image buffer, and
-// its graphs for every batch shape the trace can produce (views padded to
-// powers of two up to the reservation's, the trace's detector sizes and the
-// size classes of its projected models), captured before the run starts.
+// its graphs for every batch shape the trace can produce (view counts as
+// graph_views pads them, the trace's detector sizes and the size classes of
+// its projected models), captured before the run starts.
 gs_status prepare_graphs(gs_server *s, const gs_request *reqs, int64_t n) {
   const Limits &L = s->lim;
   if (L.views < 1) return GS_OK;
@@ -650,9 +649,9 @@ gs_status prepare_graphs(gs_server *s, const gs_request *reqs, int64_t n) {
     if (std::find(classes.begin(), classes.end(), c) == classes.end()) classes.push_back(c);
   }
   std::vector<int32_t> counts;
-  for (int32_t nb = 1;; nb *= 2) {
-    counts.push_back(std::min(nb, L.views));
-    if (nb >= L.views) break;
+  for (int32_t nv = 1; nv <= L.views; ++nv) {
+    const int32_t nb = graph_views(nv, L.views);
+    if (counts.empty() || counts.back() != nb) counts.push_back(nb);
   }
   const size_t vs_bytes = (sizeof(gsk::DevView) + sizeof(gsk::ViewSet)) * (size_t)L.views;
   const size_t img_floats = (size_t)L.views * L.width * L.height;
