@@ -758,8 +758,6 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *_
         const float dx0 = ox - pu, dy0 = oy - pv;
         // per column, the cascaded sums over the rows of e G
         float A[kSub], B[kSub], C[kSub];
-#pragma unroll
-        for (int col = 0; col < kSub; ++col) A[col] = B[col] = C[col] = 0.f;
         if (chain) {
           float e_row = __builtin_amdgcn_exp2f(dx0 * (c00 * dx0 + c01 * dy0) + c11 * dy0 * dy0);
           float rx_row = __builtin_amdgcn_exp2f(c00 * (2.f * dx0 + 1.f) + c01 * dy0);
@@ -767,8 +765,41 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *_
           const float rxx = __builtin_amdgcn_exp2f(2.f * c00);
           const float rxy = __builtin_amdgcn_exp2f(c01);
           const float ryy = __builtin_amdgcn_exp2f(2.f * c11);
+          // rows 0 and 1 start the cascade without zeroed sums: after row 0,
+          // A = B = C = e G; row 1 forms B and C from that
+          {
+            float g[kSub];
+            load_row8(s_G + goff, g);
+            float ev = e_row, rx = rx_row;
+#pragma unroll
+            for (int col = 0; col < kSub; ++col) {
+              A[col] = ((ev >= ethr) ? ev : 0.f) * g[col];
+              ev *= rx;
+              rx *= rxx;
+            }
+            e_row *= hr;
+            hr *= ryy;
+            rx_row *= rxy;
+          }
+          {
+            float g[kSub];
+            load_row8(s_G + goff + kTile, g);
+            float ev = e_row, rx = rx_row;
+#pragma unroll
+            for (int col = 0; col < kSub; ++col) {
+              const float a = fmaf((ev >= ethr) ? ev : 0.f, g[col], A[col]);
+              B[col] = A[col] + a;
+              C[col] = A[col] + B[col];
+              A[col] = a;
+              ev *= rx;
+              rx *= rxx;
+            }
+            e_row *= hr;
+            hr *= ryy;
+            rx_row *= rxy;
+          }
 #pragma unroll 2
-          for (int r = 0; r < kSub; ++r) {
+          for (int r = 2; r < kSub; ++r) {
             float g[kSub];
             load_row8(s_G + goff + r * kTile, g);
             float ev = e_row, rx = rx_row;
@@ -786,6 +817,8 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *_
             rx_row *= rxy;
           }
         } else {
+#pragma unroll
+          for (int col = 0; col < kSub; ++col) A[col] = B[col] = C[col] = 0.f;
           const float dd = 2.f * c00;
           const float thr = a.thr;
 #pragma unroll 2
