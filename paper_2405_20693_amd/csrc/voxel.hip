@@ -479,7 +479,8 @@ void launch_vox_fwd(const VoxArgs &a, const Rec3 *rec, const uint32_t *list,
 // 64 and every chained value stays a normal FP32 number; the others evaluate
 // exp2(q') per voxel.  The two kinds are queued apart (each pair's path is
 // its own).  Moments are summed per x column first (dx is constant down a
-// column) and combined once per walk.
+// column) with cascaded sums over the rows and a fold over the planes, and
+// combined once per walk.
 constexpr float kVChainRange = 120.f;
 
 __device__ inline float vox_form_max(const float (*s)[kBlock], int i, float x0, float y0,
@@ -573,10 +574,43 @@ __global__ __launch_bounds__(kBlock) void k_vox_bwd(VoxArgs a, const Rec3 *__res
           const float c00 = s[3][e], c01 = s[4][e], c02 = s[5][e], c11 = s[6][e], c12 = s[7][e],
                       c22 = s[8][e];
           const float dx0 = ox - cx, dy0 = oy - cy, dz0 = oz - cz;
-          // per x column: sums of H e times 1, dy, dz, dy^2, dy dz, dz^2
-          float C0[kVSub], Cy[kVSub], Cz[kVSub], Cyy[kVSub], Cyz[kVSub], Czz[kVSub];
+          // Per x column, a cascade over each z plane's four rows of s = e H:
+          // A += s, B += A, C += B (after the rows: row y weighted by 1, 4 - y
+          // and (4 - y)(5 - y)/2), folded over the planes into the sums of A,
+          // Z A, Z^2 A, B, Z B and C (Z = z - 1.5); the first row and plane
+          // start the sums.
+          float A[kVSub], B[kVSub], C[kVSub];
+          float M0[kVSub], MZ[kVSub], MZZ[kVSub], SB[kVSub], SZB[kVSub], SC[kVSub];
+          auto acc_row = [&](int y, const float (&se)[kVSub], const float (&h)[kVSub]) {
 #pragma unroll
-          for (int x = 0; x < kVSub; ++x) C0[x] = Cy[x] = Cz[x] = Cyy[x] = Cyz[x] = Czz[x] = 0.f;
+            for (int x = 0; x < kVSub; ++x) {
+              if (y == 0) {
+                A[x] = se[x] * h[x];
+              } else if (y == 1) {
+                const float a1 = fmaf(se[x], h[x], A[x]);
+                B[x] = A[x] + a1;
+                C[x] = A[x] + B[x];
+                A[x] = a1;
+              } else {
+                A[x] = fmaf(se[x], h[x], A[x]);
+                B[x] += A[x];
+                C[x] += B[x];
+              }
+            }
+          };
+          auto fold_plane = [&](int z) {
+            const float Z = (float)z - 0.5f * (kVSub - 1);
+#pragma unroll
+            for (int x = 0; x < kVSub; ++x) {
+              if (z == 0) {
+                M0[x] = A[x]; MZ[x] = Z * A[x]; MZZ[x] = (Z * Z) * A[x];
+                SB[x] = B[x]; SZB[x] = Z * B[x]; SC[x] = C[x];
+              } else {
+                M0[x] += A[x]; MZ[x] = fmaf(Z, A[x], MZ[x]); MZZ[x] = fmaf(Z * Z, A[x], MZZ[x]);
+                SB[x] += B[x]; SZB[x] = fmaf(Z, B[x], SZB[x]); SC[x] += C[x];
+              }
+            }
+          };
           if (chain) {
             float e_z = __builtin_amdgcn_exp2f(dx0 * (c00 * dx0 + c01 * dy0 + c02 * dz0) +
                                                dy0 * (c11 * dy0 + c12 * dz0) + c22 * dz0 * dz0);
@@ -586,78 +620,91 @@ __global__ __launch_bounds__(kBlock) void k_vox_bwd(VoxArgs a, const Rec3 *__res
             const float rxx = __builtin_amdgcn_exp2f(2.f * c00), ryy = __builtin_amdgcn_exp2f(2.f * c11),
                         rzz = __builtin_amdgcn_exp2f(2.f * c22), rxy = __builtin_amdgcn_exp2f(c01),
                         rxz = __builtin_amdgcn_exp2f(c02), ryz = __builtin_amdgcn_exp2f(c12);
+#pragma unroll
             for (int z = 0; z < kVSub; ++z) {
-              const float dz = dz0 + (float)z, dzz = dz * dz;
               float e_y = e_z, rx_y = rx_z, hy = hy_z;
 #pragma unroll
               for (int y = 0; y < kVSub; ++y) {
-                const float dy = dy0 + (float)y, dyy = dy * dy, dyz = dy * dz;
                 const float4 Hr = *reinterpret_cast<const float4 *>(
                     s_H + ((lz0 + z) * kVTile + (ly0 + y)) * kVTile + lx0);
                 const float Hx[kVSub] = {Hr.x, Hr.y, Hr.z, Hr.w};
+                float se[kVSub];
                 float ev = e_y, rx = rx_y;
 #pragma unroll
                 for (int x = 0; x < kVSub; ++x) {
-                  const float he = (ev >= ethr) ? ev * Hx[x] : 0.f;
-                  C0[x] += he;
-                  Cy[x] = fmaf(he, dy, Cy[x]);
-                  Cz[x] = fmaf(he, dz, Cz[x]);
-                  Cyy[x] = fmaf(he, dyy, Cyy[x]);
-                  Cyz[x] = fmaf(he, dyz, Cyz[x]);
-                  Czz[x] = fmaf(he, dzz, Czz[x]);
+                  se[x] = (ev >= ethr) ? ev : 0.f;
                   ev *= rx;
                   rx *= rxx;
                 }
+                acc_row(y, se, Hx);
                 e_y *= hy;
                 hy *= ryy;
                 rx_y *= rxy;
               }
+              fold_plane(z);
               e_z *= hz;
               hz *= rzz;
               hy_z *= ryz;
               rx_z *= rxz;
             }
           } else {
+#pragma unroll
             for (int z = 0; z < kVSub; ++z) {
-              const float dz = oz + (float)z - cz, dzz = dz * dz;
+              const float dz = oz + (float)z - cz;
+#pragma unroll
               for (int y = 0; y < kVSub; ++y) {
-                const float dy = oy + (float)y - cy, dyy = dy * dy, dyz = dy * dz;
+                const float dy = oy + (float)y - cy;
                 const float *Hrow = s_H + ((lz0 + z) * kVTile + (ly0 + y)) * kVTile + lx0;
+                float se[kVSub], Hx[kVSub];
 #pragma unroll
                 for (int x = 0; x < kVSub; ++x) {
                   const float dx = ox + (float)x - cx;
                   const float q = dx * (c00 * dx + c01 * dy + c02 * dz) + dy * (c11 * dy + c12 * dz) +
                                   c22 * dz * dz;
-                  const float ex = __builtin_amdgcn_exp2f(q);
-                  const float he = (q >= a.thr) ? Hrow[x] * ex : 0.f;
-                  C0[x] += he;
-                  Cy[x] = fmaf(he, dy, Cy[x]);
-                  Cz[x] = fmaf(he, dz, Cz[x]);
-                  Cyy[x] = fmaf(he, dyy, Cyy[x]);
-                  Cyz[x] = fmaf(he, dyz, Cyz[x]);
-                  Czz[x] = fmaf(he, dzz, Czz[x]);
+                  se[x] = (q >= a.thr) ? __builtin_amdgcn_exp2f(q) : 0.f;
+                  Hx[x] = Hrow[x];
                 }
+                acc_row(y, se, Hx);
               }
+              fold_plane(z);
             }
           }
-          float m[10];
-#pragma unroll
-          for (int k = 0; k < 10; ++k) m[k] = 0.f;
+          // Sums over the columns (X = x - 1.5), the moments about the
+          // sub-cube centre (L_ijk: weight X^i Y^j Z^k; with u = 4 - y =
+          // 2.5 - Y, B sums s u and 2 C - B sums s u^2), then shifted to the
+          // pair's centre: d = centre offset + (X, Y, Z).
+          float sM0 = 0.f, sXM0 = 0.f, sXXM0 = 0.f, sMZ = 0.f, sXMZ = 0.f, sMZZ = 0.f;
+          float sSB = 0.f, sXSB = 0.f, sSZB = 0.f, sSC = 0.f;
 #pragma unroll
           for (int x = 0; x < kVSub; ++x) {
-            const float dx = dx0 + (float)x;
-            m[0] += C0[x];
-            const float t = C0[x] * dx;
-            m[1] += t;
-            m[4] = fmaf(t, dx, m[4]);
-            m[2] += Cy[x];
-            m[5] = fmaf(Cy[x], dx, m[5]);
-            m[3] += Cz[x];
-            m[6] = fmaf(Cz[x], dx, m[6]);
-            m[7] += Cyy[x];
-            m[8] += Cyz[x];
-            m[9] += Czz[x];
+            const float X = (float)x - 0.5f * (kVSub - 1);
+            sM0 += M0[x];
+            sXM0 = fmaf(X, M0[x], sXM0);
+            sXXM0 = fmaf(X * X, M0[x], sXXM0);
+            sMZ += MZ[x];
+            sXMZ = fmaf(X, MZ[x], sXMZ);
+            sMZZ += MZZ[x];
+            sSB += SB[x];
+            sXSB = fmaf(X, SB[x], sXSB);
+            sSZB += SZB[x];
+            sSC += SC[x];
           }
+          const float L010 = fmaf(2.5f, sM0, -sSB), L110 = fmaf(2.5f, sXM0, -sXSB);
+          const float L011 = fmaf(2.5f, sMZ, -sSZB);
+          const float L020 = fmaf(6.25f, sM0, fmaf(-6.f, sSB, 2.f * sSC));
+          const float xc = dx0 + 0.5f * (kVSub - 1), yc = dy0 + 0.5f * (kVSub - 1),
+                      zc = dz0 + 0.5f * (kVSub - 1);
+          float m[10];
+          m[0] = sM0;
+          m[1] = fmaf(xc, sM0, sXM0);
+          m[2] = fmaf(yc, sM0, L010);
+          m[3] = fmaf(zc, sM0, sMZ);
+          m[4] = fmaf(xc, sXM0 + m[1], sXXM0);
+          m[5] = fmaf(yc, m[1], fmaf(xc, L010, L110));
+          m[6] = fmaf(zc, m[1], fmaf(xc, sMZ, sXMZ));
+          m[7] = fmaf(yc, L010 + m[2], L020);
+          m[8] = fmaf(zc, m[2], fmaf(yc, sMZ, L011));
+          m[9] = fmaf(zc, sMZ + m[3], sMZZ);
           if (active)
             for (int k = 0; k < 10; ++k) s_acc[w][k][e] += m[k];
         }
