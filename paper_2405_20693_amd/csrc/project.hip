@@ -900,7 +900,7 @@ void launch_render_bwd(const ProjArgs &a, const Rec2 *rec, const uint2 *list,
 // perspective division and t = W p + t0.  Writes the chunk's partial
 // gradients with respect to p, s, R and rho (16 values, component-major);
 // k_proj_chain_reduce sums the chunks in order and finishes the quaternion.
-constexpr int kChainViews = 8;
+constexpr int kChainViews = 16;
 constexpr int kChainParts = 16;  // gradient parts; +2 with statistics (NDC norm sum, views)
 
 // A wave's 64 consecutive Gaussians own one contiguous run of slots per view
