@@ -311,13 +311,37 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
           if (act) {
             const float pu = s_pu[j], pv = s_pv[j], fa = s_fa[j], fb = s_fb[j], fc = s_fc[j];
             const float ia = s_ia[j], ic = s_ic[j];
+            // the minimum of the form over each sub-tile's pixel-centre
+            // rectangle (rect_min_form), with the terms of its column and of
+            // its row formed once for the two sub-tiles that share them
+            float x0[2], x1[2], xe[2], ys[2], y0[2], y1[2], ye[2], xs[2];
+            bool xin[2], yin[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+              const int sx = tx * kTile + k * kSub, sy = ty * kTile + k * kSub;
+              x0[k] = (float)sx - pu;
+              x1[k] = (float)(sx + kSub - 1) - pu;
+              y0[k] = (float)sy - pv;
+              y1[k] = (float)(sy + kSub - 1) - pv;
+              xin[k] = x0[k] <= 0.f && x1[k] >= 0.f;
+              yin[k] = y0[k] <= 0.f && y1[k] >= 0.f;
+              xe[k] = x0[k] > 0.f ? x0[k] : x1[k];
+              ye[k] = y0[k] > 0.f ? y0[k] : y1[k];
+              ys[k] = -fb * xe[k] * ic;  // the minimising y on the facing x edge
+              xs[k] = -fb * ye[k] * ia;  // the minimising x on the facing y edge
+            }
             uint32_t m = 0;
 #pragma unroll
             for (int w = 0; w < 4; ++w) {
-              const int sx = tx * kTile + (w & 1) * kSub, sy = ty * kTile + (w >> 1) * kSub;
-              const float f = rect_min_form(fa, fb, fc, ia, ic, (float)sx - pu,
-                                            (float)(sx + kSub - 1) - pu, (float)sy - pv,
-                                            (float)(sy + kSub - 1) - pv);
+              const int c = w & 1, r = w >> 1;
+              float f = 0.f;
+              if (!(xin[c] && yin[r])) {
+                // clamps to the edges (y0 < y1, x0 < x1), one med3 each
+                const float dy = __builtin_amdgcn_fmed3f(ys[c], y0[r], y1[r]);
+                const float dx = __builtin_amdgcn_fmed3f(xs[r], x0[c], x1[c]);
+                f = fminf(fa * xe[c] * xe[c] + fb * xe[c] * dy + fc * dy * dy,
+                          fa * dx * dx + fb * dx * ye[r] + fc * ye[r] * ye[r]);
+              }
               m |= (f <= a.qmax ? 1u : 0u) << w;
             }
             ent = make_uint2((uint32_t)(gk + j) | (m << kEntryMaskShift), base + e);
