@@ -422,11 +422,14 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
                                                        const uint32_t *__restrict__ tile_start,
                                                        float *__restrict__ image,
                                                        float *__restrict__ partial) {
-  // staged records, relative to the tile centre: (K0, K1, K2, c00) of the
-  // exponent q' + log2|rho_hat| = K0 + K1 x + K2 y + c00 x^2 + c01 x y + c11 y^2,
-  // (c01, c11, exp2(2 c11), sign(rho_hat) exp2(threshold + log2|rho_hat|)),
-  // (threshold + log2|rho_hat|, the least exponent the multiplicative walk
-  // accepts), and the entry's sub-tile mask (empty for a zero density)
+  // staged records, relative to the tile centre, for the exponent
+  // q' + log2|rho_hat| = K0 + K1 x + K2 y + c00 x^2 + c01 x y + c11 y^2:
+  // (Pt = K0 + (kShift^2 + hs^2)(c00 + c11), K1, K2, c00), (c01, c11,
+  // sign(rho_hat) S, -et' S) of the cutoff factor for the threshold
+  // et = exp2(threshold + log2|rho_hat|), (threshold + log2|rho_hat|, the
+  // least exponent the multiplicative walk accepts, or +inf when et is too
+  // small for the factor), and the entry's sub-tile mask (empty for a zero
+  // density)
   __shared__ float4 s_r0[kBlock], s_r1[kBlock];
   __shared__ float2 s_r2[kBlock];
   __shared__ uint8_t s_m[kBlock];
@@ -448,6 +451,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
   const int sx0 = tx * kTile + (w & 1) * kSub, sy0 = ty * kTile + (w >> 1) * kSub;
   const int px = sx0 + (lane & 7), py = sy0 + (lane >> 3);
   const float hs = 0.5f * (kSub - 1);
+  constexpr float kShift = 0.5f * (kTile - kSub);  // sub-tile centre from the tile centre
   // the tile centre, and the sub-tile centre relative to it
   const float cxt = (float)(tx * kTile) + 0.5f * (kTile - 1), cyt = (float)(ty * kTile) + 0.5f * (kTile - 1);
   const float du = (float)((w & 1) * kSub) + hs - 0.5f * (kTile - 1);
@@ -517,10 +521,20 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
       const float U = r0.x - cxt, V = r0.y - cyt;
       const float K0 = U * (c00 * U + c01 * V) + c11 * V * V + lr;
       const float K1 = -(2.f * c00 * U + c01 * V), K2 = -(c01 * U + 2.f * c11 * V);
-      s_r0[tid] = make_float4(K0, K1, K2, c00);
-      s_r1[tid] = make_float4(c01, c11, __builtin_amdgcn_exp2f(2.f * c11),
-                              copysignf(__builtin_amdgcn_exp2f(thr + lr), rho));
-      s_r2[tid] = make_float2(thr + lr, fmaxf(lr, 0.f) - kFwdChainRange);
+      // the sub-tile centres lie at (+-kShift, +-kShift) from the tile
+      // centre: Pt + du K1 + dv K2 + du dv c01 is the exponent at a sub-tile
+      // centre plus hs^2 (c00 + c11)
+      const float Pt = fmaf(kShift * kShift + hs * hs, c00 + c11, K0);
+      // the cutoff factor's scale S and offset -et' S (et = 0: no cutoff,
+      // m = 1); thresholds under 2^-100 keep the per-pixel path
+      const float et = __builtin_amdgcn_exp2f(thr + lr);
+      const uint32_t etb = __float_as_uint(et) >> 23;  // biased exponent
+      const float S = et > 0.f ? __uint_as_float((278u - etb) << 23) : 0.f;
+      const float cS = et > 0.f ? -__uint_as_float(__float_as_uint(et) - 1u) * S : 1.f;
+      const bool chain_ok = et == 0.f || etb >= 27u;
+      s_r0[tid] = make_float4(Pt, K1, K2, c00);
+      s_r1[tid] = make_float4(c01, c11, copysignf(S, rho), cS);
+      s_r2[tid] = make_float2(thr + lr, chain_ok ? fmaxf(lr, 0.f) - kFwdChainRange : INFINITY);
       s_m[tid] = rho != 0.f ? (uint8_t)(ex >> kEntryMaskShift) : (uint8_t)0;
     }
     ex_next = base + kBlock + tid < end ? list[base + kBlock + tid].x : 0u;
@@ -539,24 +553,18 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
         const float c00 = r0.w, c01 = r1.x, c11 = r1.y;
         const float K1 = fmaf(2.f * c00, du, fmaf(c01, dv, r0.y));
         const float K2 = fmaf(c01, du, fmaf(2.f * c11, dv, r0.z));
-        const float K0 = r0.x + du * r0.y + dv * r0.z + du * (c00 * du + c01 * dv) + c11 * dv * dv;
-        const float A0 = K0 - hs * K2 + hs * hs * c11, A1 = K1 - hs * c01;
-        const float B0 = K2 + c11 * (1.f - 2.f * hs);
+        // P: the exponent at the sub-tile centre plus hs^2 (c00 + c11)
+        const float P = fmaf(du, r0.y, fmaf(dv, r0.z, fmaf(du * dv, c01, r0.x)));
+        const float A0 = fmaf(-hs, K2, fmaf(-hs * hs, c00, P)), A1 = fmaf(-hs, c01, K1);
+        const float B0 = fmaf(c11, 1.f - 2.f * hs, K2);
         // the least exponent over the sub-tile is at a corner (+-hs, +-hs):
         // P + c +- a on one diagonal, P - c +- b on the other
-        const float P = fmaf(hs * hs, c00 + c11, K0);
         const float ea = hs * (K1 + K2), eb = hs * (K1 - K2), ec = hs * hs * c01;
         const float qmin = P + fminf(ec - fabsf(ea), -ec - fabsf(eb));
-        // the cutoff factor's scale S and offset -et' S (et = 0: no cutoff,
-        // m = 1); thresholds under 2^-100 keep the per-pixel path
-        const float et = fabsf(r1.w);
-        const uint32_t etb = __float_as_uint(et) >> 23;  // biased exponent
-        const float S = et > 0.f ? __uint_as_float((278u - etb) << 23) : 0.f;
-        const float cS = et > 0.f ? -__uint_as_float(__float_as_uint(et) - 1u) * S : 1.f;
-        chain = qmin >= r2.y && (et == 0.f || etb >= 27u);
+        chain = qmin >= r2.y;
         k0 = make_float4(A0, A1, c00, B0);
-        k1 = chain ? make_float4(c01, r1.z, copysignf(S, r1.w), cS)
-                   : make_float4(c01, 2.f * c11, r2.x, copysignf(1.f, r1.w));
+        k1 = chain ? make_float4(c01, __builtin_amdgcn_exp2f(2.f * c11), r1.z, r1.w)
+                   : make_float4(c01, 2.f * c11, r2.x, copysignf(1.f, r1.z));
       }
       // compact: multiplicative records from the front, the others from the back
       const uint64_t mc = __ballot(hit && chain), me = __ballot(hit && !chain);
