@@ -727,10 +727,6 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *_
     }
     ent_cur = ent_next;
     ent_next = (base + 2 * kBlock + tid < end) ? list[base + 2 * kBlock + tid] : make_uint2(0u, 0u);
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-#pragma unroll
-      for (int ww = 0; ww < 4; ++ww) s_acc[ww][k][tid] = 0.f;
     __syncthreads();
     // Compact the records whose entry mask marks this wave's sub-tile (the
     // cutoff ellipse meets it; set by the scatter) into two queues.
@@ -906,10 +902,21 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(ProjArgs a, const Rec2 *_
     }
     __syncthreads();
     if (tid < n && my_slot < a.cap) {
+      // every sub-tile the entry's mask marks was walked and wrote its
+      // moments; the others count as zero (their accumulators hold older
+      // batches' values, cleared here bit by bit, without a branch)
+      const uint32_t mk = s_m[tid];
+      const int z0 = -(int)(mk & 1u), z1 = -(int)((mk >> 1) & 1u), z2 = -(int)((mk >> 2) & 1u),
+                z3 = -(int)((mk >> 3) & 1u);
       float *o = slots + (int64_t)my_slot * 6;
 #pragma unroll
-      for (int k = 0; k < 6; ++k)
-        o[k] = ((s_acc[0][k][tid] + s_acc[1][k][tid]) + s_acc[2][k][tid]) + s_acc[3][k][tid];
+      for (int k = 0; k < 6; ++k) {
+        const float a0 = __int_as_float(__float_as_int(s_acc[0][k][tid]) & z0);
+        const float a1 = __int_as_float(__float_as_int(s_acc[1][k][tid]) & z1);
+        const float a2 = __int_as_float(__float_as_int(s_acc[2][k][tid]) & z2);
+        const float a3 = __int_as_float(__float_as_int(s_acc[3][k][tid]) & z3);
+        o[k] = ((a0 + a1) + a2) + a3;
+      }
     }
   }
 }
