@@ -269,3 +269,40 @@ def test_graph_replays_across_runs_and_batches(ops):
             a, b = alone.cpu().numpy(), r["out"].cpu().numpy()
             assert np.all(np.isfinite(b))
             assert np.abs(a - b).max() <= 1e-5 * max(float(np.abs(a).max()), 1e-30)
+
+
+@pytest.mark.parametrize("graphs", [False, True])
+def test_overflowing_batches_are_served_again_alone(ops, graphs):
+    """Aligned prolate Gaussians bin into 2.7 times more tile entries seen
+    side-on (theta = pi/2: 1308) than end-on (theta = 0: 487; counts of the
+    oracle's projection).  The server sizes its reservation from the first
+    request of the model, end-on, with a 1.25 margin per view, so batches of
+    side-on views overflow their tile lists.  Such a batch is detected from
+    the entries the device needed and its requests are served again one by
+    one (each fits alone): every request succeeds and equals the same request
+    run alone, with direct launches and with graph replay."""
+    rng = np.random.default_rng(5)
+    m = 400
+    needles = scenes.gaussians(rng.uniform(-0.4, 0.4, (m, 3)),
+                               np.tile([0.25, 0.012, 0.012], (m, 1)),
+                               np.tile([1.0, 0.0, 0.0, 0.0], (m, 1)), rng.uniform(0.5, 1.0, m))
+    dm = _dev(needles)
+    srv = ops.Server(n_workers=1, batching=True, max_batch_views=16, hbm_budget_bytes=1 << 30,
+                     graphs=graphs)
+    srv.add_model(*dm)
+    reqs = []
+    for i in range(33):
+        th = [0.0] if i == 0 else [np.pi / 2 + 0.01 * i]
+        reqs.append({"kind": "project", "model": 0, "arrival_s": 0.0,
+                     "views": ops.Views.cone(th, 13.64, 20.46, 48, 48, 0.05),
+                     "out": torch.full((1, 48, 48), float("nan"), device="cuda")})
+    res, wall = srv.run(reqs, time_scale=0.0)
+    torch.cuda.synchronize()
+    assert all(r["status"] == 0 for r in res)
+    assert sum(1 for r in res[1:] if r["batch_size"] == 1) > 0  # served again alone
+    for r in reqs:
+        alone = ops.project_forward(*dm, r["views"], 3.0, ops.Plan())
+        torch.cuda.synchronize()
+        a, b = alone.cpu().numpy(), r["out"].cpu().numpy()
+        assert np.all(np.isfinite(b))
+        assert np.abs(a - b).max() <= 1e-5 * max(float(np.abs(a).max()), 1e-30)
