@@ -433,6 +433,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
   __shared__ float4 s_r0[kBlock], s_r1[kBlock];
   __shared__ float2 s_r2[kBlock];
   __shared__ uint8_t s_m[kBlock];
+  __shared__ uint8_t s_h[4][kBlock];  // per wave: the batch's records that mark its sub-tile
   // per wave: the kept records' coefficients, compacted, two float4 each in
   // two arrays, so that the eight groups read eight consecutive float4:
   // multiplicative records queue from the front, per-pixel exp2 records from
@@ -539,9 +540,20 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(ProjArgs a, const Rec2 *_
     }
     ex_next = base + kBlock + tid < end ? list[base + kBlock + tid].x : 0u;
     __syncthreads();
+    // the indices of the batch's records that mark this wave's sub-tile, in
+    // entry order, so that the chunks below are whole chunks of them
+    int nh = 0;
     for (int c0 = 0; c0 < n; c0 += 64) {
       const int i = c0 + lane;
-      const bool hit = i < n && ((s_m[i] >> w) & 1u);
+      const bool h = i < n && ((s_m[i] >> w) & 1u);
+      const uint64_t mh = __ballot(h);
+      if (h) s_h[w][nh + lanes_below(mh)] = (uint8_t)i;
+      nh += __popcll(mh);
+    }
+    wave_lds_order();
+    for (int c0 = 0; c0 < nh; c0 += 64) {
+      const bool hit = c0 + lane < nh;
+      const int i = hit ? (int)s_h[w][c0 + lane] : 0;
       bool chain = false;
       float4 k0, k1;
       if (hit) {
