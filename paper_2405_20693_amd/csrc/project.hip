@@ -1,6 +1,8 @@
 // X-ray rasterizer kernels: per-(view, Gaussian) projection with tile
 // histograms, tile-list scatter, tile render forward/backward and the
 // per-Gaussian chain rule (paper Sec. 3.2.1, Eq. 5-7, App. A).
+#include <utility>
+
 #include "internal.h"
 
 namespace gsk {
@@ -961,6 +963,28 @@ constexpr int kChainParts = 16;  // gradient parts; +2 with statistics (NDC norm
 // last load.
 constexpr int kChainStage = 512;         // float4 per wave (8 KB)
 constexpr uint32_t kChainRound = 340u;   // slots per staging round
+constexpr int kChainLoads = kChainStage / 64;  // 16-byte loads per lane and round
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// A round's float4 i = I * 64 + lane into register I (indices fixed at
+// compile time, so the array stays in registers).  Lanes past the round
+// reload its last float4: with a branch around each load the compiler waits
+// for every load before issuing the next, and the round then costs up to
+// eight memory latencies instead of one.
+template <int... I>
+__device__ __forceinline__ void chain_round_load(f32x4 (&r)[kChainLoads], const float4 *src,
+                                                 int lane, int n4, std::integer_sequence<int, I...>) {
+  const f32x4 *s = reinterpret_cast<const f32x4 *>(src);
+  ((r[I] = s[min(I * 64 + lane, n4 - 1)]), ...);
+}
+// ... and all of them to the wave's staging buffer of kChainStage float4
+// (the copies past the round land where the round's sums never read).
+template <int... I>
+__device__ __forceinline__ void chain_round_stage(const f32x4 (&r)[kChainLoads], float4 *dst,
+                                                  int lane, std::integer_sequence<int, I...>) {
+  f32x4 *d = reinterpret_cast<f32x4 *>(dst);
+  ((d[I * 64 + lane] = r[I]), ...);
+}
 
 __global__ __launch_bounds__(kBlock) void k_proj_chain(ProjArgs a,
                                                        const uint32_t *__restrict__ offsets,
@@ -1014,10 +1038,10 @@ __global__ __launch_bounds__(kBlock) void k_proj_chain(ProjArgs a,
         const uint64_t chi = min((uint64_t)hi, clo + kChainRound);
         const uint64_t b4 = (clo * 6u) >> 2, e4 = (chi * 6u + 3u) >> 2;
         const int n4 = (int)(e4 - b4);
-#pragma unroll
-        for (int it = 0; it < kChainStage / 64; ++it) {
-          const int i = it * 64 + lane;
-          if (i < n4) s_st[w][i] = slots4[b4 + i];
+        {
+          f32x4 r[kChainLoads];
+          chain_round_load(r, slots4 + b4, lane, n4, std::make_integer_sequence<int, kChainLoads>{});
+          chain_round_stage(r, s_st[w], lane, std::make_integer_sequence<int, kChainLoads>{});
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();

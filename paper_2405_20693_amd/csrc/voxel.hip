@@ -753,7 +753,20 @@ __global__ __launch_bounds__(kBlock) void k_vox_chain(VoxArgs a,
     float S[10];
     for (int k = 0; k < 10; ++k) S[k] = 0.f;
     const float *sl = slots + (int64_t)off * 10;
-    for (int i = 0; i < cnt; ++i)
+    // four slots' loads in flight at a time, added in slot order
+    int i = 0;
+    for (; i + 4 <= cnt; i += 4) {
+      float t[4][10];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int k = 0; k < 10; ++k) t[u][k] = sl[10 * (i + u) + k];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int k = 0; k < 10; ++k) S[k] += t[u][k];
+    }
+    for (; i < cnt; ++i)
       for (int k = 0; k < 10; ++k) S[k] += sl[10 * i + k];
     const float *h = a.spacing;
     // world-unit moments
