@@ -255,17 +255,22 @@ __global__ __launch_bounds__(kBlock) void k_proj_scatter(ProjArgs a, const Rec2 
       s_mask[t] = 0;
     }
     base = chunk_start[v * a.C + c];
+    // each batch's records are loaded one batch ahead (zero past the set)
+    Rec2 r_next{};
+    if (g0 + tid < S.M) r_next = rec[S.rbase + g0 + tid];
     for (int k = 0; k < a.cpt; ++k) {
       const int64_t gk = g0 + (int64_t)k * kBlock;
       if (gk >= S.M) break;
       const int64_t g = gk + tid;
       const bool valid = g < S.M;
-      Rect2 rc{1, 0, 0, 0};
-      Rec2 r{};
-      if (valid) {
-        r = rec[S.rbase + g];
-        rc = unpack_rect(r.r0, r.r1);
+      const Rec2 r = r_next;
+      if (k + 1 < a.cpt) {
+        Rec2 rn{};
+        if (g + kBlock < S.M) rn = rec[S.rbase + g + kBlock];
+        r_next = rn;
       }
+      Rect2 rc{1, 0, 0, 0};
+      if (valid) rc = unpack_rect(r.r0, r.r1);
       const int n = valid ? rect_count(rc) : 0;
       uint32_t total;
       const uint32_t ex = block_excl_scan((uint32_t)n, sh4, total);  // synchronizes the workgroup
